@@ -1,0 +1,206 @@
+"""FP64 CPU oracle for the D3Q19 BGK update (ctypes wrapper around d3q19_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: the oracle is what the GPU library is checked
+against.  Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg
+of ``bench.py`` may import it.  It shares no code with the HIP library and
+imports nothing from it.
+
+The method it implements is the paper's Eq. 1-3 (Section 2, "Lattice Boltzmann
+Method") in the fused two-array form of Section 3.1, on the D3Q19 velocity set,
+with Guo forcing and halfway bounce-back; ``d3q19_oracle.c`` lists each step
+and each reading of the paper.
+
+Array conventions (all numpy, C-contiguous):
+  state S   float64, shape (19, nz, ny, nx), unshifted populations
+  flags     uint8,   shape (nz, ny, nx), 0 fluid / 1 solid (None: all fluid)
+  rho       float64, shape (nz, ny, nx)
+  u         float64, shape (3, nz, ny, nx)  (u_x, u_y, u_z)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "d3q19_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle_d3q19.so")
+
+Q = 19
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (FP64, no fast-math, no contraction)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
+               "-fno-fast-math", "-Wall", "-o", _LIB, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        d = ctypes.POINTER(ctypes.c_double)
+        u8 = ctypes.POINTER(ctypes.c_uint8)
+        i32 = ctypes.POINTER(ctypes.c_int)
+        ci = ctypes.c_int
+        lib.oracle_q.restype = ci
+        lib.oracle_lattice.argtypes = [i32, d, i32]
+        lib.oracle_feq.argtypes = [ctypes.c_double, d, d]
+        lib.oracle_source.argtypes = [ctypes.c_double, d, d, d]
+        lib.oracle_init.argtypes = [ci, ci, ci, u8, d, d, d]
+        lib.oracle_step.argtypes = [ci, ci, ci, u8, ctypes.c_double, d, d, d, d, d, d]
+        lib.oracle_run.argtypes = [ci, ci, ci, u8, ctypes.c_double, d, d, d, ci]
+        lib.oracle_run.restype = ci
+        lib.oracle_macros.argtypes = [ci, ci, ci, u8, d, d, d, d, d]
+        lib.oracle_sums.argtypes = [ci, ci, ci, u8, d, d]
+        _lib = lib
+    return _lib
+
+
+def _dp(a):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _fp(flags, shape):
+    if flags is None:
+        return None
+    assert flags.dtype == np.uint8 and flags.flags.c_contiguous and flags.shape == shape
+    return flags.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+
+
+def _vec3(F):
+    if F is None:
+        return None
+    return np.ascontiguousarray(np.asarray(F, dtype=np.float64).reshape(3))
+
+
+def lattice():
+    """Return (c[19,3] int, w[19] float64, opp[19] int) as the oracle defines them."""
+    lib = _load()
+    c = np.zeros((Q, 3), dtype=np.int32)
+    w = np.zeros(Q, dtype=np.float64)
+    opp = np.zeros(Q, dtype=np.int32)
+    lib.oracle_lattice(c.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _dp(w),
+                       opp.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+    return c, w, opp
+
+
+def feq(rho: float, u) -> np.ndarray:
+    """Eq. 2-3 equilibrium for one site."""
+    out = np.zeros(Q)
+    _load().oracle_feq(float(rho), _dp(_vec3(u)), _dp(out))
+    return out
+
+
+def source(omega: float, u, F) -> np.ndarray:
+    """Guo source term S_i for one site."""
+    out = np.zeros(Q)
+    _load().oracle_source(float(omega), _dp(_vec3(u)), _dp(_vec3(F)), _dp(out))
+    return out
+
+
+def init(shape, rho=None, u=None, flags=None) -> np.ndarray:
+    """S_0 = f^eq(rho, u) at fluid sites, f = w at solid sites."""
+    nz, ny, nx = shape
+    S = np.zeros((Q, nz, ny, nx))
+    rho = None if rho is None else np.ascontiguousarray(rho, dtype=np.float64)
+    u = None if u is None else np.ascontiguousarray(u, dtype=np.float64)
+    _load().oracle_init(nx, ny, nz, _fp(flags, (nz, ny, nx)), _dp(rho), _dp(u), _dp(S))
+    return S
+
+
+def step(S, tau, F=None, flags=None, Fx_field=None, moments=False):
+    """One fused step; returns S' (and (rho, u) pre-collision moments if asked)."""
+    _, nz, ny, nx = S.shape
+    S = np.ascontiguousarray(S, dtype=np.float64)
+    out = np.empty_like(S)
+    rho = np.empty((nz, ny, nx)) if moments else None
+    u = np.empty((3, nz, ny, nx)) if moments else None
+    fx = None if Fx_field is None else np.ascontiguousarray(Fx_field, dtype=np.float64)
+    _load().oracle_step(nx, ny, nz, _fp(flags, (nz, ny, nx)), 1.0 / tau, _dp(_vec3(F)), _dp(fx),
+                        _dp(S), _dp(out), _dp(rho), _dp(u))
+    return (out, rho, u) if moments else out
+
+
+def run(S, tau, nsteps, F=None, flags=None, Fx_field=None) -> np.ndarray:
+    """n steps; returns the new state (the input array is not modified)."""
+    _, nz, ny, nx = S.shape
+    S = np.array(S, dtype=np.float64, order="C", copy=True)
+    fx = None if Fx_field is None else np.ascontiguousarray(Fx_field, dtype=np.float64)
+    rc = _load().oracle_run(nx, ny, nz, _fp(flags, (nz, ny, nx)), 1.0 / tau, _dp(_vec3(F)),
+                            _dp(fx), _dp(S), int(nsteps))
+    if rc != 0:
+        raise MemoryError("oracle_run: allocation failed")
+    return S
+
+
+def macros(S, F=None, flags=None, Fx_field=None):
+    """(rho, u) of a stored post-collision state (Guo identity form)."""
+    _, nz, ny, nx = S.shape
+    S = np.ascontiguousarray(S, dtype=np.float64)
+    rho = np.empty((nz, ny, nx))
+    u = np.empty((3, nz, ny, nx))
+    fx = None if Fx_field is None else np.ascontiguousarray(Fx_field, dtype=np.float64)
+    _load().oracle_macros(nx, ny, nz, _fp(flags, (nz, ny, nx)), _dp(_vec3(F)), _dp(fx), _dp(S),
+                          _dp(rho), _dp(u))
+    return rho, u
+
+
+def sums(S, flags=None) -> np.ndarray:
+    """[sum S, sum c_x S, sum c_y S, sum c_z S] over fluid sites."""
+    _, nz, ny, nx = S.shape
+    S = np.ascontiguousarray(S, dtype=np.float64)
+    out = np.zeros(4)
+    _load().oracle_sums(nx, ny, nz, _fp(flags, (nz, ny, nx)), _dp(S), _dp(out))
+    return out
+
+
+def run_window(rho, u, flags, tau, nsteps, centres, F=None):
+    """Light-cone evaluation of single sites after ``nsteps`` steps.
+
+    A site's value after n steps depends only on the initial state within
+    L-infinity distance n (every D3Q19 velocity moves at most one site per
+    axis per step).  For each centre (z, y, x) this cuts the (2n+1)-wide
+    window around it out of the periodic initial fields (the whole axis when
+    it is no wider than that), runs the oracle on the window alone and returns
+    (rho, u) at the centre.  Errors from the window's own artificial wrap
+    travel inward one site per step and reach distance n-1 from the edge at
+    most, so the centre is exact.  Returns rho[k], u[k, 3].
+    """
+    nz, ny, nx = rho.shape
+    W = 2 * nsteps + 1
+    out_r = np.empty(len(centres))
+    out_u = np.empty((len(centres), 3))
+    for k, (cz, cy, cx) in enumerate(centres):
+        idx = []
+        cen = []
+        for c, n in ((cz, nz), (cy, ny), (cx, nx)):
+            if n <= W:
+                idx.append(np.arange(n))
+                cen.append(c)
+            else:
+                idx.append((np.arange(W) + c - nsteps) % n)
+                cen.append(nsteps)
+        iz, iy, ix = np.ix_(*idx)
+        r_w = np.ascontiguousarray(rho[iz, iy, ix], dtype=np.float64)
+        u_w = np.ascontiguousarray(u[:, iz, iy, ix], dtype=np.float64)
+        f_w = None if flags is None else np.ascontiguousarray(flags[iz, iy, ix])
+        S = init(r_w.shape, r_w, u_w, f_w)
+        S = run(S, tau, nsteps, F=F, flags=f_w)
+        r_o, u_o = macros(S, F=F, flags=f_w)
+        out_r[k] = r_o[cen[0], cen[1], cen[2]]
+        out_u[k] = u_o[:, cen[0], cen[1], cen[2]]
+    return out_r, out_u

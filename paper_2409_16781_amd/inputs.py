@@ -1,0 +1,116 @@
+"""Seeded synthetic inputs for the lattice workloads.
+
+This module only builds initial fields and flag masks (plain trigonometry,
+seeded random numbers and geometry); it holds none of the lattice Boltzmann
+arithmetic.  The same arrays feed the GPU library and the FP64 oracle.
+
+Workloads (all lattice units):
+
+* Taylor-Green vortex, uniform in z (the paper lists the Taylor-Green vortex
+  among the mini-app's use cases, Section 3.3 "Use Cases"):
+      u_x =  u0 sin(k x) cos(k y),  u_y = -u0 cos(k x) sin(k y),  u_z = 0,
+      rho = 1 + (3 u0^2 / 4) (cos 2kx + cos 2ky),   k = 2 pi / n
+  with x, y the integer node indices (pressure of the incompressible vortex,
+  rho = 1 + 3 p for sound speed squared 1/3).
+* Channel: solid planes y = 0 and y = ny - 1, periodic in x and z (no-slip
+  walls, the boundary type of the paper's lid-driven cavity, Section 3.3).
+* Porous channel: channel walls plus seeded random spheres to a target
+  porosity.
+* Noise: i.i.d. uniform in [-a, a], drawn once in float64 with
+  ``numpy.random.default_rng(seed)`` in C order (component, z, y, x).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def tgv_fields(nx: int, ny: int, nz: int, u0: float):
+    """Taylor-Green vortex (uniform in z).  Returns rho (nz,ny,nx), u (3,nz,ny,nx), float64."""
+    if nx != ny:
+        raise ValueError("the Taylor-Green workload uses a square x-y cross-section")
+    k = 2.0 * math.pi / nx
+    x = np.arange(nx, dtype=np.float64)
+    y = np.arange(ny, dtype=np.float64)
+    sx, cx = np.sin(k * x), np.cos(k * x)
+    sy, cy = np.sin(k * y), np.cos(k * y)
+    ux2 = u0 * np.outer(cy, sx)            # (ny, nx): sin(kx) cos(ky)
+    uy2 = -u0 * np.outer(sy, cx)           # -cos(kx) sin(ky)
+    r2 = 1.0 + 0.75 * u0 * u0 * (np.cos(2 * k * x)[None, :] + np.cos(2 * k * y)[:, None])
+    rho = np.broadcast_to(r2, (nz, ny, nx)).copy()
+    u = np.zeros((3, nz, ny, nx))
+    u[0] = ux2
+    u[1] = uy2
+    return rho, u
+
+
+def uniform_noise(shape, amplitude: float, seed: int) -> np.ndarray:
+    """i.i.d. uniform noise in [-amplitude, amplitude], float64, C order."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(-amplitude, amplitude, size=shape)
+
+
+def channel_flags(nx: int, ny: int, nz: int) -> np.ndarray:
+    """uint8 flags (nz, ny, nx): solid planes at y = 0 and y = ny - 1."""
+    f = np.zeros((nz, ny, nx), dtype=np.uint8)
+    f[:, 0, :] = 1
+    f[:, ny - 1, :] = 1
+    return f
+
+
+def random_flags(nx: int, ny: int, nz: int, fraction: float, seed: int) -> np.ndarray:
+    """uint8 flags with each site solid with probability ``fraction`` (test geometry)."""
+    rng = np.random.default_rng(seed)
+    return (rng.random((nz, ny, nx)) < fraction).astype(np.uint8)
+
+
+def sphere_flags(nx: int, ny: int, nz: int, porosity: float, seed: int,
+                 rmin: float = 2.0, rmax: float = 6.0, walls: bool = True) -> np.ndarray:
+    """Channel (optional walls at y = 0, ny-1) filled with random periodic spheres.
+
+    Sphere centres are uniform over the box and radii uniform in [rmin, rmax];
+    spheres are added until the fluid fraction drops to ``porosity`` or below.
+    """
+    rng = np.random.default_rng(seed)
+    f = channel_flags(nx, ny, nz) if walls else np.zeros((nz, ny, nx), dtype=np.uint8)
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    total = nx * ny * nz
+    for _ in range(100000):
+        if 1.0 - f.sum() / total <= porosity:
+            break
+        c = rng.uniform(0, 1, 3) * np.array([nx, ny, nz])
+        r = rng.uniform(rmin, rmax)
+        dx = np.abs(x - c[0]); dx = np.minimum(dx, nx - dx)
+        dy = np.abs(y - c[1]); dy = np.minimum(dy, ny - dy)
+        dz = np.abs(z - c[2]); dz = np.minimum(dz, nz - dz)
+        f[(dx * dx + dy * dy + dz * dz) <= r * r] = 1
+    return f
+
+
+# --- the named workloads -------------------------------------------------------
+
+def tgv_box(n: int = 32, u0: float = 0.01, tau: float = 0.8, steps: int = 200):
+    """Periodic n^3 Taylor-Green vortex, no noise (32^3, tau 0.8, 200 steps)."""
+    rho, u = tgv_fields(n, n, n, u0)
+    return dict(name=f"tgv{n}", shape=(n, n, n), rho=rho, u=u, flags=None, tau=tau,
+                force=(0.0, 0.0, 0.0), steps=steps)
+
+
+def channel(nx: int = 256, ny: int = 128, nz: int = 128, tau: float = 0.6, g: float = 1e-6,
+            steps: int = 5000, noise: float = 1e-4, seed: int = 1):
+    """Force-driven channel: walls at y = 0 and ny-1, rho = 1 + U(+-noise), u = 0."""
+    rho = 1.0 + uniform_noise((nz, ny, nx), noise, seed)
+    u = np.zeros((3, nz, ny, nx))
+    return dict(name=f"channel{nx}x{ny}x{nz}", shape=(nz, ny, nx), rho=rho, u=u,
+                flags=channel_flags(nx, ny, nz), tau=tau, force=(g, 0.0, 0.0), steps=steps)
+
+
+def tgv_noise_box(n: int = 512, u0: float = 0.01, tau: float = 0.55, steps: int = 1000,
+                  noise: float = 1e-3, seed: int = 2):
+    """Periodic n^3 Taylor-Green vortex plus i.i.d. U(+-noise) on every velocity component."""
+    rho, u = tgv_fields(n, n, n, u0)
+    if noise:
+        u += uniform_noise(u.shape, noise, seed)
+    return dict(name=f"tgv{n}_noise", shape=(n, n, n), rho=rho, u=u, flags=None, tau=tau,
+                force=(0.0, 0.0, 0.0), steps=steps)
