@@ -1,0 +1,179 @@
+#!/usr/bin/env python3
+"""Throughput of the fused D3Q19 BGK step on one MI355X.
+
+Workload: 512^3 periodic lattice, Taylor-Green vortex (u0 = 0.01,
+k = 2 pi / 512) plus seeded uniform +-1e-3 noise on every velocity component,
+tau = 0.55, no body force; populations stored as FP32, FP16 or BF16 (shifted
+by the lattice weights), FP32 arithmetic, FP64 conservation totals every step.
+A step is one launch of the fused update over all 134,217,728 sites with the
+inputs already resident in HBM.
+
+Prints one JSON line: MLUPS of the FP32-storage path as ``value``, the
+16-bit-storage results beside it, the HBM roofline of the step kernel
+(algorithmic bytes: 19 loads + 19 stores per site), a copy-kernel ceiling
+measured in the same run, and the FP64 oracle timed on the host cores on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=200)
+    p.add_argument("--warmup", type=int, default=20)
+    p.add_argument("--n", type=int, default=512, help="lattice edge (default 512)")
+    p.add_argument("--codecs", default="f32,f16,bf16")
+    p.add_argument("--cpu-steps", type=int, default=3, help="oracle steps in the CPU baseline sample")
+    p.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
+    p.add_argument("--reps", type=int, default=3, help="timed repetitions (median reported)")
+    return p.parse_args()
+
+
+def workload_fields(n):
+    from paper_2409_16781_amd import inputs
+    cfg = inputs.tgv_noise_box(n, u0=0.01, tau=0.55, steps=1000, noise=1e-3, seed=2)
+    return cfg
+
+
+def bytes_per_site(codec):
+    return 19 * 2 * (4 if codec == "f32" else 2)
+
+
+def run_codec(torch, lbm, cfg, codec, steps, warmup, reps):
+    n = cfg["shape"][0]
+    N = n ** 3
+    lat = lbm.Lattice(n, n, n, cfg["tau"], codec=codec)
+    rho = torch.from_numpy(cfg["rho"]).cuda()
+    u = torch.from_numpy(cfg["u"]).cuda()
+    lat.init_eq(rho, u)
+    del rho, u
+    torch.cuda.synchronize()
+    log(f"[bench] {codec}: variant={lat.info} warmup={warmup}")
+    lat.step(warmup)
+    lat.sync()
+    times = []
+    for r in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ms = lat.time_steps(steps)     # HIP events on the lattice stream around the K launches
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        times.append((ms, wall))
+        log(f"[bench] {codec}: rep {r}: {ms:.2f} ms for {steps} steps (wall {wall * 1e3:.2f} ms)")
+    ms_med = sorted(t[0] for t in times)[len(times) // 2]
+    wall_med = sorted(t[1] for t in times)[len(times) // 2]
+    per_step_ms = ms_med / steps
+    mlups = N * steps / (ms_med * 1e-3) / 1e6
+    gbs = bytes_per_site(codec) * N / (per_step_ms * 1e-3) / 1e9
+    copy_ms = lat.copy_probe(10)
+    copy_bytes = 2 * 19 * lat.info["plane"] * lat.info["bytes_per_population"]
+    copy_gbs = copy_bytes / (copy_ms * 1e-3) / 1e9
+    sums = lat.sums(min(steps, 4096))
+    drift = float(abs(sums[-1, 0] - sums[0, 0]) / sums[0, 0])
+    r_out, u_out = lat.macros()
+    torch.cuda.synchronize()
+    res = dict(codec=codec, mlups=mlups, ms_per_step=per_step_ms, wall_ms=wall_med * 1e3,
+               achieved_gbs=gbs, frac_hbm=gbs / HBM_PEAK_GBS, copy_gbs=copy_gbs,
+               frac_copy=gbs / copy_gbs, mass_drift_per_step=drift / max(1, len(sums) - 1),
+               variant=lat.info["variant"], sites_per_thread=lat.info["sites_per_thread"],
+               grid=lat.info["grid"], steps_done=lat.steps_done)
+    lat.close()
+    return res, u_out
+
+
+def cpu_baseline(cfg, steps):
+    """The FP64 oracle as it stands, on the host cores, for a few steps of the same lattice."""
+    import oracle
+    oracle.build(force=False)
+    n = cfg["shape"][0]
+    S = oracle.init(cfg["shape"], cfg["rho"], cfg["u"], None)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    S = oracle.run(S, cfg["tau"], steps)
+    dt = time.perf_counter() - t0
+    del S
+    return dict(value=n ** 3 * steps / dt / 1e6, unit="MLUPS", cores=threads, kind="oracle",
+                sample=f"{n}^3 lattice of the same workload, {steps} FP64 steps, {dt:.1f} s")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    import paper_2409_16781_amd as lbm
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    n = args.n
+    log(f"[bench] generating {n}^3 Taylor-Green + noise inputs")
+    cfg = workload_fields(n)
+    results = {}
+    u_fields = {}
+    for codec in args.codecs.split(","):
+        res, u = run_codec(torch, lbm, cfg, codec, args.steps, args.warmup, args.reps)
+        results[codec] = res
+        u_fields[codec] = u
+        log(f"[bench] {codec}: {res['mlups']:.0f} MLUPS, {res['achieved_gbs']:.0f} GB/s "
+            f"({100 * res['frac_hbm']:.1f}% of HBM peak, {100 * res['frac_copy']:.1f}% of copy)")
+    # FP16 / BF16 vs FP32 after the same number of steps (GPU vs GPU, not parity)
+    if "f32" in u_fields:
+        ref = u_fields["f32"].double()
+        for c in u_fields:
+            if c != "f32":
+                d = (u_fields[c].double() - ref).norm() / ref.norm()
+                results[c]["rel_l2_u_vs_f32"] = float(d)
+    del u_fields
+    torch.cuda.empty_cache()
+
+    main_codec = "f32" if "f32" in results else list(results)[0]
+    m = results[main_codec]
+    N = n ** 3
+    line = {
+        "metric": "D3Q19 MLUPS & % HBM peak at 512³: FP32 vs FP16-store, equal-accuracy",
+        "value": round(m["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(m["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"D3Q19 BGK periodic {n}^3 Taylor-Green (u0=0.01) + seeded U(+-1e-3) "
+                               f"velocity noise, tau=0.55, {main_codec} storage, FP64 GPU totals per step",
+                   "sites": N, "storage": main_codec, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(m["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(m["frac_hbm"], 4), "traffic": None,
+                     "bytes_per_site": bytes_per_site(main_codec),
+                     "copy_ceiling_gbs": round(m["copy_gbs"], 1), "frac_of_copy": round(m["frac_copy"], 4)},
+        "variants": {c: {k: (round(v, 6) if isinstance(v, float) else v) for k, v in r.items()}
+                     for c, r in results.items()},
+    }
+    if "f16" in results and "f32" in results:
+        line["f16_over_f32_mlups"] = round(results["f16"]["mlups"] / results["f32"]["mlups"], 3)
+    if not args.no_cpu:
+        log(f"[bench] CPU baseline: oracle, {args.cpu_steps} steps")
+        line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_steps)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,197 @@
+/*
+ * lb.h -- C ABI of the MI355X D3Q19 lattice Boltzmann library.
+ *
+ * The library advances a D3Q19 BGK lattice with the fused collide-and-stream
+ * update of the paper (arXiv 2409.16781): Eq. 1 (lattice Boltzmann equation),
+ * Eq. 2-3 (second-order equilibrium), Section 3.1 (fused kernel with a
+ * scattered read from the pre-collision array, a write into the
+ * post-collision array and a swap; one unit-stride vector per population),
+ * Section 3.1.1 (storage precision, "Mixed1": half-precision storage with
+ * single-precision arithmetic).  On top of the paper's two-dimensional method
+ * it provides the three-dimensional D3Q19 velocity set, halfway bounce-back
+ * at solid sites (the no-slip walls of Section 3.3), periodic faces, and a
+ * uniform body force in Guo's form as the source term S_i of Eq. 1.
+ *
+ * Conventions shared by every call:
+ *  - Lattice sites are indexed s = x + nx * (y + ny * z), x fastest.
+ *  - Population order (also the layout of lb_get_f / lb_set_f):
+ *      0 (0,0,0); 1 (+1,0,0); 2 (-1,0,0); 3 (0,+1,0); 4 (0,-1,0); 5 (0,0,+1);
+ *      6 (0,0,-1); 7 (+1,+1,0); 8 (+1,-1,0); 9 (-1,+1,0); 10 (-1,-1,0);
+ *      11 (+1,0,+1); 12 (+1,0,-1); 13 (-1,0,+1); 14 (-1,0,-1); 15 (0,+1,+1);
+ *      16 (0,+1,-1); 17 (0,-1,+1); 18 (0,-1,-1).
+ *    Weights: 1/3 (rest), 1/18 (axis), 1/36 (diagonal).
+ *  - The stored state is the post-collision population array.  It is kept
+ *    shifted by the lattice weights, g_i = f_i - w_i, in the storage codec
+ *    chosen at creation (FP32, or FP16 / BF16 rounded to nearest even); all
+ *    arithmetic is FP32.
+ *  - "Device" pointers are HIP device memory owned by the caller; the library
+ *    never frees them.  Calls that take device pointers are enqueued on the
+ *    lattice's stream and return before the work completes.
+ *  - Every int-returning call returns LB_OK (0) or a negative status code and
+ *    records a message readable with lb_last_error() on the calling thread.
+ *    No C++ exception crosses this interface.
+ *  - A handle may be used from one thread at a time; handles are independent.
+ */
+#ifndef LB_H
+#define LB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lb_lattice lb_lattice;
+
+/* Status codes. */
+#define LB_OK 0
+#define LB_EINVAL (-1)    /* an argument is out of range or inconsistent        */
+#define LB_ENOMEM (-2)    /* device or host allocation failed                   */
+#define LB_EHIP (-3)      /* a HIP runtime call failed (no device, launch error) */
+#define LB_EUNSTABLE (-4) /* a conservation sum is NaN or infinite              */
+#define LB_ESTATE (-5)    /* the handle is not a live lattice                   */
+
+/* Storage codecs (Section 3.1.1: storage precision vs. arithmetic precision). */
+#define LB_F32 0   /* FP32 storage of g = f - w, 4 bytes per population      */
+#define LB_F16S 1  /* FP16 storage of g = f - w, round-to-nearest-even        */
+#define LB_BF16S 2 /* BF16 storage of g = f - w, round-to-nearest-even        */
+
+/* Memory spaces for lb_get_f / lb_set_f. */
+#define LB_HOST 0
+#define LB_DEVICE 1
+
+/*
+ * Create a lattice of nx * ny * nz sites with relaxation time tau (omega =
+ * 1/tau, kinematic viscosity (tau - 1/2)/3; Eq. 1).  tau must be > 0.5, or
+ * +INFINITY, which gives omega = 0 (pure streaming).  flags is a HOST pointer
+ * to nx*ny*nz bytes, 0 = fluid, 1 = solid (no-slip obstacle or wall; any other
+ * value is rejected), copied by the call; NULL means all fluid.  Every face
+ * is periodic.  The lattice starts at rest (g = 0) with zero force and FP32
+ * storage, on the default HIP stream.  Device memory for two population
+ * arrays and the flag masks is allocated here and owned by the lattice.
+ * Returns NULL on failure (see lb_last_error()).
+ */
+lb_lattice *lb_create(int nx, int ny, int nz, double tau, const uint8_t *flags);
+
+/*
+ * As lb_create, with a storage codec (LB_F32, LB_F16S, LB_BF16S) and a HIP
+ * stream (hipStream_t passed as void*) on which all of the lattice's work is
+ * enqueued.  NULL is the default stream.  The stream is borrowed: the
+ * lattice never destroys it, and it must outlive the lattice.
+ */
+lb_lattice *lb_create_ex(int nx, int ny, int nz, double tau, const uint8_t *flags, int storage,
+                         void *hip_stream);
+
+/* Release everything the lattice owns (waits for its stream first).  NULL is
+ * a no-op.  A destroyed handle must not be used again. */
+void lb_destroy(lb_lattice *lat);
+
+/*
+ * Uniform body-force density F (lattice units, per site per step), entering
+ * as Guo's source term S_i = (1 - omega/2) w_i [3 (c_i - u) + 9 (c_i.u) c_i].F
+ * with the velocity u = (sum_i c_i f_i + F/2) / rho (the paper's source term
+ * S_i of Eq. 1, Section 2).  Applies to the steps enqueued after the call.
+ */
+int lb_set_force(lb_lattice *lat, double fx, double fy, double fz);
+
+/*
+ * Set the state to the equilibrium of Eq. 2-3 at every fluid site:
+ * f_i = f_i^eq(rho, u), computed in FP64 and rounded once into the storage
+ * codec.  rho: device array of N doubles (NULL: rho = 1); u: device array of
+ * 3N doubles, component-major (N values of u_x, then u_y, then u_z; NULL:
+ * u = 0).  Solid sites are set to rest.  Resets the step count to 0.
+ */
+int lb_init_eq(lb_lattice *lat, const double *rho, const double *u);
+
+/*
+ * Enqueue n >= 0 fused steps (Eq. 1, Section 3.1): for every fluid site x,
+ *   f_i = S_i(x - c_i), or S_opp(i)(x) when x - c_i is solid (bounce-back),
+ *   rho = sum f_i,  u = (sum c_i f_i + F/2)/rho,
+ *   S'_i(x) = f_i - omega (f_i - f_i^eq) + S_i^F,
+ * then swap the arrays.  Each step also records the FP64 totals of the new
+ * state (see lb_sums).  Long runs are replayed from a captured HIP graph.
+ */
+int lb_step(lb_lattice *lat, int n);
+
+/*
+ * As lb_step with n >= 1, and the last step also writes the density and
+ * velocity it computes (the pre-collision moments of that step, u including
+ * the half-force shift) into caller-owned device arrays rho (N floats) and u
+ * (3N floats, component-major).  Solid sites get rho = 0, u = 0.
+ */
+int lb_step_macros(lb_lattice *lat, int n, float *rho, float *u);
+
+/*
+ * Density and velocity of the current state, into caller-owned device arrays
+ * rho (N floats) and u (3N floats, component-major):
+ *   rho = sum_i f_i,   u = (sum_i c_i f_i - F/2) / rho.
+ * After a step these equal the pre-collision moments of that step (collision
+ * keeps mass and the source adds exactly F to the momentum).  Solid sites get
+ * rho = 0, u = 0.  Either pointer may be NULL to skip it.
+ */
+int lb_macros(lb_lattice *lat, float *rho, float *u);
+
+/*
+ * Copy the conservation totals of the last k steps into out[4*k] (host),
+ * oldest first: {mass, momentum_x, momentum_y, momentum_z} summed over fluid
+ * sites of each step's stored state (sum of f_i = w_i + g_i and of c_i g_i, as
+ * stored), accumulated in FP64 on the GPU in a fixed order (bitwise
+ * reproducible).  k must be <= min(steps taken since lb_init_eq, 4096).
+ * Synchronises the stream.  Returns LB_EUNSTABLE when any copied value is
+ * NaN or infinite (the values are still copied).
+ */
+int lb_sums(lb_lattice *lat, double *out, int k);
+
+/*
+ * Raw state in storage format: 19 planes of N elements (plane i = population
+ * i, site order as above), each element the codec's value of g_i = f_i - w_i
+ * (float for LB_F32, IEEE binary16 for LB_F16S, bfloat16 for LB_BF16S).
+ * bytes must equal 19 * N * (4 or 2).  where is LB_HOST or LB_DEVICE.
+ * Host copies synchronise; device copies are enqueued.  lb_set_f leaves the
+ * step count unchanged.  Values at solid sites are carried but never used.
+ */
+int lb_get_f(lb_lattice *lat, void *buf, size_t bytes, int where);
+int lb_set_f(lb_lattice *lat, const void *buf, size_t bytes, int where);
+
+/* Wait until all work enqueued on the lattice's stream has finished. */
+int lb_sync(lb_lattice *lat);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *lb_last_error(void);
+
+/* ---- queries and measurement helpers -------------------------------------- */
+
+/* Number of steps taken since lb_init_eq (host count of enqueued steps). */
+long long lb_steps_done(const lb_lattice *lat);
+
+/*
+ * Integer properties: key 0 = kernel variant of the step (0 = one site per
+ * thread, 1 / 2 / 3 = vector rows with 16- / 8- / 4-byte accesses per lane
+ * and population plane), 1 = sites per thread, 2 = 1 if the lattice has
+ * solid sites, 3 = bytes per stored population, 4 = workgroups per step
+ * launch, 5 = plane stride in elements, 6 = number of fluid sites.
+ * Returns -1 for an unknown key or a bad handle.
+ */
+long long lb_query(const lb_lattice *lat, int key);
+
+/*
+ * Enqueue n steps between two HIP events recorded on the lattice's stream,
+ * wait for them, and store the elapsed milliseconds in *ms.
+ */
+int lb_time_steps(lb_lattice *lat, int n, double *ms);
+
+/*
+ * Bandwidth ceiling probe: a 16-byte-per-lane streaming copy of the current
+ * population array into the other one (the same bytes a step reads and
+ * writes), run reps times between HIP events on the lattice's stream.
+ * Stores the mean milliseconds per copy in *ms.  Overwrites only the scratch
+ * array, so the state is unchanged.
+ */
+int lb_copy_probe(lb_lattice *lat, int reps, double *ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LB_H */

@@ -1,0 +1,230 @@
+"""MI355X D3Q19 lattice Boltzmann library: Python binding of the C ABI in include/lb.h.
+
+The binding only marshals arguments: every step of the update runs in the
+HIP kernels of ``liblbm355.so``.  PyTorch provides device memory and the
+stream; there is no CPU fallback, and importing ``Lattice`` without the built
+library raises.
+
+Array conventions (torch tensors on the GPU, C-contiguous):
+  rho  (nz, ny, nx)      float64 in, float32 out
+  u    (3, nz, ny, nx)   float64 in, float32 out (u_x, u_y, u_z)
+  f    (19, nz, ny, nx)  raw storage: float32 (LB_F32) or 16-bit words
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "liblbm355.so")
+
+LB_OK, LB_EINVAL, LB_ENOMEM, LB_EHIP, LB_EUNSTABLE, LB_ESTATE = 0, -1, -2, -3, -4, -5
+LB_F32, LB_F16S, LB_BF16S = 0, 1, 2
+LB_HOST, LB_DEVICE = 0, 1
+CODECS = {"f32": LB_F32, "f16": LB_F16S, "bf16": LB_BF16S}
+
+# Every function the C ABI exports, with its ctypes signature.
+_P = ctypes.c_void_p
+_SIGNATURES = {
+    "lb_create": (_P, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, _P]),
+    "lb_create_ex": (_P, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, _P, ctypes.c_int, _P]),
+    "lb_destroy": (None, [_P]),
+    "lb_set_force": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
+    "lb_init_eq": (ctypes.c_int, [_P, _P, _P]),
+    "lb_step": (ctypes.c_int, [_P, ctypes.c_int]),
+    "lb_step_macros": (ctypes.c_int, [_P, ctypes.c_int, _P, _P]),
+    "lb_macros": (ctypes.c_int, [_P, _P, _P]),
+    "lb_sums": (ctypes.c_int, [_P, _P, ctypes.c_int]),
+    "lb_get_f": (ctypes.c_int, [_P, _P, ctypes.c_size_t, ctypes.c_int]),
+    "lb_set_f": (ctypes.c_int, [_P, _P, ctypes.c_size_t, ctypes.c_int]),
+    "lb_sync": (ctypes.c_int, [_P]),
+    "lb_last_error": (ctypes.c_char_p, []),
+    "lb_steps_done": (ctypes.c_longlong, [_P]),
+    "lb_query": (ctypes.c_longlong, [_P, ctypes.c_int]),
+    "lb_time_steps": (ctypes.c_int, [_P, ctypes.c_int, _P]),
+    "lb_copy_probe": (ctypes.c_int, [_P, ctypes.c_int, _P]),
+}
+
+_lib = None
+
+
+class LBError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        super().__init__(f"{where} failed ({code}): {msg}")
+        self.code = code
+
+
+def lib() -> ctypes.CDLL:
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2409_16781_amd._build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().lb_last_error().decode()
+
+
+def _check(rc: int, where: str):
+    if rc != LB_OK:
+        raise LBError(rc, where, last_error())
+    return rc
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Lattice:
+    """A D3Q19 lattice on the GPU (owns the library handle).
+
+    ``stream``: a torch.cuda.Stream, or None for torch's current stream.
+    """
+
+    def __init__(self, nx: int, ny: int, nz: int, tau: float, flags=None, codec: str = "f32", stream=None):
+        import torch
+
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.n = self.nx * self.ny * self.nz
+        self.codec = codec
+        if codec not in CODECS:
+            raise ValueError(f"codec must be one of {sorted(CODECS)}")
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        fl = None
+        if flags is not None:
+            fl = np.ascontiguousarray(flags, dtype=np.uint8)
+            if fl.shape != (self.nz, self.ny, self.nx):
+                raise ValueError("flags must have shape (nz, ny, nx)")
+        self._flags = fl
+        h = lib().lb_create_ex(self.nx, self.ny, self.nz, float(tau),
+                               None if fl is None else fl.ctypes.data_as(ctypes.c_void_p),
+                               CODECS[codec], ctypes.c_void_p(self._stream.cuda_stream))
+        if not h:
+            raise LBError(LB_EINVAL, "lb_create_ex", last_error())
+        self._h = ctypes.c_void_p(h)
+
+    # -- lifetime -----------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().lb_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    # -- ABI calls ----------------------------------------------------------
+    def set_force(self, fx: float, fy: float = 0.0, fz: float = 0.0):
+        _check(lib().lb_set_force(self._h, float(fx), float(fy), float(fz)), "lb_set_force")
+
+    def init_eq(self, rho=None, u=None):
+        """rho (nz,ny,nx), u (3,nz,ny,nx): float64 CUDA tensors (or None)."""
+        import torch
+
+        for t, shape in ((rho, (self.nz, self.ny, self.nx)), (u, (3, self.nz, self.ny, self.nx))):
+            if t is not None:
+                if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != shape:
+                    raise ValueError(f"expected a contiguous float64 CUDA tensor of shape {shape}")
+        _check(lib().lb_init_eq(self._h, _ptr(rho), _ptr(u)), "lb_init_eq")
+
+    def step(self, n: int = 1):
+        _check(lib().lb_step(self._h, int(n)), "lb_step")
+
+    def step_macros(self, n: int = 1):
+        """n steps; the last one also returns its (rho, u) as float32 tensors."""
+        import torch
+
+        rho = torch.empty((self.nz, self.ny, self.nx), dtype=torch.float32, device="cuda")
+        u = torch.empty((3, self.nz, self.ny, self.nx), dtype=torch.float32, device="cuda")
+        _check(lib().lb_step_macros(self._h, int(n), _ptr(rho), _ptr(u)), "lb_step_macros")
+        return rho, u
+
+    def macros(self):
+        import torch
+
+        rho = torch.empty((self.nz, self.ny, self.nx), dtype=torch.float32, device="cuda")
+        u = torch.empty((3, self.nz, self.ny, self.nx), dtype=torch.float32, device="cuda")
+        _check(lib().lb_macros(self._h, _ptr(rho), _ptr(u)), "lb_macros")
+        return rho, u
+
+    def sums(self, k: int = 1) -> np.ndarray:
+        out = np.zeros((k, 4), dtype=np.float64)
+        rc = lib().lb_sums(self._h, out.ctypes.data_as(ctypes.c_void_p), int(k))
+        if rc == LB_EUNSTABLE:
+            raise LBError(rc, "lb_sums", last_error())
+        _check(rc, "lb_sums")
+        return out
+
+    def _raw_dtype(self):
+        return np.float32 if self.codec == "f32" else np.uint16
+
+    def get_f(self) -> np.ndarray:
+        """Raw stored state on the host: (19, nz, ny, nx) float32 or uint16 words."""
+        out = np.empty((19, self.nz, self.ny, self.nx), dtype=self._raw_dtype())
+        _check(lib().lb_get_f(self._h, out.ctypes.data_as(ctypes.c_void_p), out.nbytes, LB_HOST), "lb_get_f")
+        return out
+
+    def set_f(self, f: np.ndarray):
+        f = np.ascontiguousarray(f, dtype=self._raw_dtype())
+        if f.shape != (19, self.nz, self.ny, self.nx):
+            raise ValueError("state must have shape (19, nz, ny, nx)")
+        _check(lib().lb_set_f(self._h, f.ctypes.data_as(ctypes.c_void_p), f.nbytes, LB_HOST), "lb_set_f")
+
+    def get_f_device(self, out):
+        _check(lib().lb_get_f(self._h, _ptr(out), out.numel() * out.element_size(), LB_DEVICE), "lb_get_f")
+
+    def set_f_device(self, f):
+        _check(lib().lb_set_f(self._h, _ptr(f), f.numel() * f.element_size(), LB_DEVICE), "lb_set_f")
+
+    def sync(self):
+        _check(lib().lb_sync(self._h), "lb_sync")
+
+    @property
+    def steps_done(self) -> int:
+        return int(lib().lb_steps_done(self._h))
+
+    def query(self, key: int) -> int:
+        return int(lib().lb_query(self._h, int(key)))
+
+    @property
+    def info(self) -> dict:
+        keys = ["variant", "sites_per_thread", "solids", "bytes_per_population", "grid", "plane", "n_fluid"]
+        return {k: self.query(i) for i, k in enumerate(keys)}
+
+    def time_steps(self, n: int) -> float:
+        ms = ctypes.c_double(0.0)
+        _check(lib().lb_time_steps(self._h, int(n), ctypes.byref(ms)), "lb_time_steps")
+        return ms.value
+
+    def copy_probe(self, reps: int = 10) -> float:
+        ms = ctypes.c_double(0.0)
+        _check(lib().lb_copy_probe(self._h, int(reps), ctypes.byref(ms)), "lb_copy_probe")
+        return ms.value
+
+
+def decode_state(raw: np.ndarray, codec: str) -> np.ndarray:
+    """Raw stored words -> float64 shifted populations g = f - w (host-side view)."""
+    if codec == "f32":
+        return raw.astype(np.float64)
+    if codec == "f16":
+        return raw.view(np.float16).astype(np.float64)
+    return (raw.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+WEIGHTS = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)

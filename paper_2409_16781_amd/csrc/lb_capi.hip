@@ -1,0 +1,527 @@
+// Host runtime and C ABI of the D3Q19 lattice library (declared in include/lb.h).
+//
+// A lattice owns two population arrays (the pre- and post-collision arrays of
+// the paper's fused scheme, Section 3.1), swapped by parity after every step,
+// the neighbour masks used by bounce-back, and the buffers of the per-step
+// FP64 conservation totals.  Work is enqueued on one in-order HIP stream;
+// long step sequences are replayed from a captured HIP graph.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lb.h"
+#include "lb_internal.h"
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_OR_FAIL(expr)                                                                         \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess) return fail(LB_EHIP, "%s: %s", #expr, hipGetErrorString(e_));       \
+    } while (0)
+
+constexpr uint64_t kMagic = 0x4c42443351313921ull;  // "LBD3Q19!"
+constexpr uint64_t kDead = 0xdeadd3a1deadd3a1ull;
+constexpr int kGraphSteps = 32;  // steps per captured graph (even: the graph ends on its start parity)
+
+long env_long(const char *name, long dflt)
+{
+    const char *v = getenv(name);
+    if (!v || !*v) return dflt;
+    return strtol(v, nullptr, 10);
+}
+
+}  // namespace
+
+struct lb_lattice {
+    uint64_t magic;
+    int nx, ny, nz;
+    uint64_t n;       // sites
+    uint64_t plane;   // elements between population planes
+    int codec, esize;
+    double tau, omega;
+    double force[3];
+    void *buf[2];
+    int cur;          // buf[cur] holds the state
+    uint8_t *flags;   // device copy, or nullptr when all fluid
+    uint32_t *nbmask;
+    uint8_t *rowdirty;
+    bool solids;
+    double n_fluid;
+    double *partials;
+    unsigned int *ticket;
+    double *ring;
+    unsigned long long *counter;
+    hipStream_t stream;
+    hipStream_t cap_stream;
+    int variant, vsites, grid, cus;
+    long long steps;
+    hipGraphExec_t gexec;
+    bool graph_ok;
+};
+
+namespace {
+
+int check(const lb_lattice *h)
+{
+    if (!h || h->magic != kMagic) return fail(LB_ESTATE, "invalid or destroyed lattice handle");
+    return LB_OK;
+}
+
+StepArgs step_args(const lb_lattice *h, int from, float *rho, float *u)
+{
+    StepArgs a{};
+    a.src = h->buf[from];
+    a.dst = h->buf[from ^ 1];
+    a.plane = h->plane;
+    a.nx = h->nx;
+    a.ny = h->ny;
+    a.nz = h->nz;
+    a.nslots = (int)(h->n / (uint64_t)h->vsites);
+    a.div_nx = make_fastdiv((uint32_t)h->nx);
+    a.div_ny = make_fastdiv((uint32_t)h->ny);
+    a.omega = (float)h->omega;
+    a.fx = (float)h->force[0];
+    a.fy = (float)h->force[1];
+    a.fz = (float)h->force[2];
+    a.nbmask = h->nbmask;
+    a.rowdirty = h->rowdirty;
+    a.rho_out = rho;
+    a.u_out = u;
+    a.partials = h->partials;
+    a.ticket = h->ticket;
+    a.ring = h->ring;
+    a.step_counter = h->counter;
+    a.n_fluid = h->n_fluid;
+    return a;
+}
+
+// Enqueue one step from buf[from] on stream s.
+int enqueue_one(lb_lattice *h, int from, float *rho, float *u, hipStream_t s)
+{
+    const bool macros = rho != nullptr;
+    StepArgs a = step_args(h, from, rho, u);
+    HIP_OR_FAIL(launch_step(h->codec, h->variant, h->solids, macros, a, h->grid, s));
+    if (macros && h->solids && h->variant == 0)
+        HIP_OR_FAIL(launch_zero_solid_macros(h->flags, (int)h->n, rho, u, s));
+    return LB_OK;
+}
+
+int build_graph(lb_lattice *h)
+{
+    if (h->graph_ok) return LB_OK;
+    if (h->gexec) {
+        (void)hipGraphExecDestroy(h->gexec);
+        h->gexec = nullptr;
+    }
+    if (!h->cap_stream) HIP_OR_FAIL(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    HIP_OR_FAIL(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    int rc = LB_OK;
+    for (int k = 0; k < kGraphSteps && rc == LB_OK; ++k) rc = enqueue_one(h, k & 1, nullptr, nullptr, h->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+    if (rc != LB_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(LB_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(LB_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    h->graph_ok = true;
+    return LB_OK;
+}
+
+int enqueue_steps(lb_lattice *h, int n, float *rho, float *u)
+{
+    int plain = rho ? n - 1 : n;
+    if (plain >= 2 * kGraphSteps) {
+        if (h->cur == 1) {
+            int rc = enqueue_one(h, 1, nullptr, nullptr, h->stream);
+            if (rc) return rc;
+            h->cur = 0;
+            h->steps += 1;
+            --plain;
+        }
+        int rc = build_graph(h);
+        if (rc) return rc;
+        while (plain >= kGraphSteps) {
+            HIP_OR_FAIL(hipGraphLaunch(h->gexec, h->stream));
+            h->steps += kGraphSteps;
+            plain -= kGraphSteps;
+        }
+    }
+    for (int k = 0; k < plain; ++k) {
+        int rc = enqueue_one(h, h->cur, nullptr, nullptr, h->stream);
+        if (rc) return rc;
+        h->cur ^= 1;
+        h->steps += 1;
+    }
+    if (rho) {
+        int rc = enqueue_one(h, h->cur, rho, u, h->stream);
+        if (rc) return rc;
+        h->cur ^= 1;
+        h->steps += 1;
+    }
+    return LB_OK;
+}
+
+void release(lb_lattice *h)
+{
+    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+    void *ptrs[] = {h->buf[0], h->buf[1], h->flags, h->nbmask, h->rowdirty, h->partials, h->ticket, h->ring, h->counter};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+}
+
+int create_impl(lb_lattice **out, int nx, int ny, int nz, double tau, const uint8_t *flags, int storage,
+                void *stream)
+{
+    *out = nullptr;
+    if (nx < 1 || ny < 1 || nz < 1) return fail(LB_EINVAL, "lattice extents must be >= 1 (got %d x %d x %d)", nx, ny, nz);
+    const uint64_t n = (uint64_t)nx * ny * nz;
+    if (n > 0x7fffffffull - 4096) return fail(LB_EINVAL, "lattice of %llu sites exceeds 2^31 - 4097", (unsigned long long)n);
+    if (!(tau > 0.5)) return fail(LB_EINVAL, "tau must be > 0.5 or +inf (got %g)", tau);
+    if (storage != LB_F32 && storage != LB_F16S && storage != LB_BF16S)
+        return fail(LB_EINVAL, "unknown storage codec %d", storage);
+    uint64_t nsolid = 0;
+    if (flags) {
+        for (uint64_t s = 0; s < n; ++s) {
+            if (flags[s] > 1) return fail(LB_EINVAL, "flag value %d at site %llu (allowed: 0 fluid, 1 solid)", (int)flags[s], (unsigned long long)s);
+            nsolid += flags[s];
+        }
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(LB_EHIP, "no HIP device available");
+
+    lb_lattice *h = new (std::nothrow) lb_lattice();
+    if (!h) return fail(LB_ENOMEM, "host allocation failed");
+    h->nx = nx;
+    h->ny = ny;
+    h->nz = nz;
+    h->n = n;
+    h->codec = storage;
+    h->esize = storage == LB_F32 ? 4 : 2;
+    h->tau = tau;
+    h->omega = std::isinf(tau) ? 0.0 : 1.0 / tau;
+    h->stream = reinterpret_cast<hipStream_t>(stream);
+    h->solids = nsolid > 0;
+    h->n_fluid = (double)(n - nsolid);
+
+    // Step kernel: vector rows when nx is a multiple of the sites per lane,
+    // else one site per thread.  LB_KERNEL (0..3) overrides for tuning.
+    const long kernel = env_long("LB_KERNEL", -1);
+    int variant = 2;
+    if (kernel >= 0 && kernel <= 3) variant = (int)kernel;
+    else if (kernel != -1) {
+        delete h;
+        return fail(LB_EINVAL, "LB_KERNEL must be 0, 1, 2 or 3");
+    }
+    if (variant != 0 && nx % sites_per_thread(storage, variant) != 0) {
+        if (kernel > 0) {
+            delete h;
+            return fail(LB_EINVAL, "kernel %d needs nx %% %d == 0", variant, sites_per_thread(storage, variant));
+        }
+        variant = (variant <= 2 && nx % sites_per_thread(storage, 3) == 0) ? 3 : 0;
+    }
+    h->variant = variant;
+    h->vsites = sites_per_thread(storage, h->variant);
+    // Plane stride: a multiple of 256 elements plus an optional pad that moves
+    // the planes off a common power-of-two alignment.
+    const long pad = env_long("LB_PLANE_PAD", 0);
+    if (pad < 0 || pad % 64 != 0) {
+        delete h;
+        return fail(LB_EINVAL, "LB_PLANE_PAD must be a non-negative multiple of 64");
+    }
+    h->plane = ((n + 255) / 256) * 256 + (uint64_t)pad;
+
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        delete h;
+        return fail(LB_EHIP, "cannot query the HIP device");
+    }
+    h->cus = prop.multiProcessorCount;
+    const int occ = step_occupancy(storage, h->variant, h->solids, false);
+    const long wg_per_cu = env_long("LB_WG_PER_CU", occ);
+    const uint64_t tiles = (n / h->vsites + kBlock - 1) / kBlock;
+    uint64_t grid = (uint64_t)h->cus * (uint64_t)(wg_per_cu < 1 ? 1 : wg_per_cu);
+    if (grid > tiles) grid = tiles;
+    h->grid = (int)(grid < 1 ? 1 : grid);
+
+    auto bail = [&](int code, const char *what, hipError_t e) {
+        release(h);
+        delete h;
+        return fail(code, "%s: %s", what, hipGetErrorString(e));
+    };
+    const size_t pbytes = (size_t)kQ * h->plane * h->esize;
+    hipError_t e;
+    for (int b = 0; b < 2; ++b) {
+        e = hipMalloc(&h->buf[b], pbytes);
+        if (e != hipSuccess) return bail(LB_ENOMEM, "hipMalloc(populations)", e);
+        e = hipMemsetAsync(h->buf[b], 0, pbytes, h->stream);
+        if (e != hipSuccess) return bail(LB_EHIP, "hipMemsetAsync", e);
+    }
+    // per-launch totals: one slot per workgroup of the largest grid any step uses
+    const int max_grid = h->grid > 65536 ? h->grid : 65536;
+    if ((e = hipMalloc(&h->partials, (size_t)max_grid * 4 * sizeof(double))) != hipSuccess) return bail(LB_ENOMEM, "hipMalloc", e);
+    if ((e = hipMalloc(&h->ticket, sizeof(unsigned int))) != hipSuccess) return bail(LB_ENOMEM, "hipMalloc", e);
+    if ((e = hipMalloc(&h->ring, (size_t)kRingCap * 4 * sizeof(double))) != hipSuccess) return bail(LB_ENOMEM, "hipMalloc", e);
+    if ((e = hipMalloc(&h->counter, sizeof(unsigned long long))) != hipSuccess) return bail(LB_ENOMEM, "hipMalloc", e);
+    if ((e = hipMemsetAsync(h->ticket, 0, sizeof(unsigned int), h->stream)) != hipSuccess) return bail(LB_EHIP, "hipMemsetAsync", e);
+    if ((e = hipMemsetAsync(h->counter, 0, sizeof(unsigned long long), h->stream)) != hipSuccess) return bail(LB_EHIP, "hipMemsetAsync", e);
+    if ((e = hipMemsetAsync(h->ring, 0, (size_t)kRingCap * 4 * sizeof(double), h->stream)) != hipSuccess) return bail(LB_EHIP, "hipMemsetAsync", e);
+    if (h->solids) {
+        if ((e = hipMalloc(&h->flags, n)) != hipSuccess) return bail(LB_ENOMEM, "hipMalloc(flags)", e);
+        if ((e = hipMalloc(&h->nbmask, n * sizeof(uint32_t) + 64)) != hipSuccess) return bail(LB_ENOMEM, "hipMalloc(masks)", e);
+        if ((e = hipMalloc(&h->rowdirty, (size_t)ny * nz)) != hipSuccess) return bail(LB_ENOMEM, "hipMalloc(rows)", e);
+        if ((e = hipMemcpyAsync(h->flags, flags, n, hipMemcpyHostToDevice, h->stream)) != hipSuccess) return bail(LB_EHIP, "hipMemcpyAsync(flags)", e);
+        if ((e = launch_masks(h->flags, nx, ny, nz, h->nbmask, h->rowdirty, h->stream)) != hipSuccess) return bail(LB_EHIP, "mask kernels", e);
+    }
+    if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return bail(LB_EHIP, "hipStreamSynchronize", e);
+    h->magic = kMagic;
+    *out = h;
+    return LB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *lb_last_error(void) { return g_err.c_str(); }
+
+lb_lattice *lb_create_ex(int nx, int ny, int nz, double tau, const uint8_t *flags, int storage, void *hip_stream)
+{
+    lb_lattice *h = nullptr;
+    try {
+        if (create_impl(&h, nx, ny, nz, tau, flags, storage, hip_stream) != LB_OK) return nullptr;
+    } catch (...) {
+        fail(LB_ENOMEM, "unexpected exception in lb_create");
+        return nullptr;
+    }
+    g_err.clear();
+    return h;
+}
+
+lb_lattice *lb_create(int nx, int ny, int nz, double tau, const uint8_t *flags)
+{
+    return lb_create_ex(nx, ny, nz, tau, flags, LB_F32, nullptr);
+}
+
+void lb_destroy(lb_lattice *h)
+{
+    if (!h || h->magic != kMagic) return;
+    (void)hipStreamSynchronize(h->stream);
+    h->magic = kDead;
+    release(h);
+    delete h;
+}
+
+int lb_set_force(lb_lattice *h, double fx, double fy, double fz)
+{
+    if (int rc = check(h)) return rc;
+    if (!std::isfinite(fx) || !std::isfinite(fy) || !std::isfinite(fz)) return fail(LB_EINVAL, "force must be finite");
+    h->force[0] = fx;
+    h->force[1] = fy;
+    h->force[2] = fz;
+    h->graph_ok = false;
+    return LB_OK;
+}
+
+int lb_init_eq(lb_lattice *h, const double *rho, const double *u)
+{
+    if (int rc = check(h)) return rc;
+    InitArgs a{};
+    a.dst = h->buf[0];
+    a.plane = h->plane;
+    a.n = (int)h->n;
+    a.rho = rho;
+    a.u = u;
+    a.flags = h->flags;
+    HIP_OR_FAIL(launch_init(h->codec, a, h->stream));
+    HIP_OR_FAIL(hipMemsetAsync(h->counter, 0, sizeof(unsigned long long), h->stream));
+    h->cur = 0;
+    h->steps = 0;
+    return LB_OK;
+}
+
+int lb_step(lb_lattice *h, int n)
+{
+    if (int rc = check(h)) return rc;
+    if (n < 0) return fail(LB_EINVAL, "step count must be >= 0 (got %d)", n);
+    return enqueue_steps(h, n, nullptr, nullptr);
+}
+
+int lb_step_macros(lb_lattice *h, int n, float *rho, float *u)
+{
+    if (int rc = check(h)) return rc;
+    if (n < 1) return fail(LB_EINVAL, "lb_step_macros needs n >= 1 (got %d)", n);
+    if (!rho || !u) return fail(LB_EINVAL, "rho and u must be device pointers");
+    return enqueue_steps(h, n, rho, u);
+}
+
+int lb_macros(lb_lattice *h, float *rho, float *u)
+{
+    if (int rc = check(h)) return rc;
+    MacroArgs a{};
+    a.src = h->buf[h->cur];
+    a.plane = h->plane;
+    a.n = (int)h->n;
+    a.fx = (float)h->force[0];
+    a.fy = (float)h->force[1];
+    a.fz = (float)h->force[2];
+    a.flags = h->flags;
+    a.rho = rho;
+    a.u = u;
+    HIP_OR_FAIL(launch_macros(h->codec, a, h->stream));
+    return LB_OK;
+}
+
+int lb_sums(lb_lattice *h, double *out, int k)
+{
+    if (int rc = check(h)) return rc;
+    if (k < 0 || !out) return fail(LB_EINVAL, "bad output buffer or k");
+    const long long avail = h->steps < kRingCap ? h->steps : kRingCap;
+    if (k > avail) return fail(LB_EINVAL, "asked for %d step totals, %lld available", k, avail);
+    HIP_OR_FAIL(hipStreamSynchronize(h->stream));
+    std::vector<double> ring((size_t)kRingCap * 4);
+    HIP_OR_FAIL(hipMemcpy(ring.data(), h->ring, ring.size() * sizeof(double), hipMemcpyDeviceToHost));
+    bool bad = false;
+    for (int j = 0; j < k; ++j) {
+        const long long step = h->steps - k + j;
+        const double *r = &ring[4 * (size_t)(step % kRingCap)];
+        for (int c = 0; c < 4; ++c) {
+            out[4 * j + c] = r[c];
+            if (!std::isfinite(r[c])) bad = true;
+        }
+    }
+    if (bad) return fail(LB_EUNSTABLE, "conservation totals contain NaN or Inf");
+    return LB_OK;
+}
+
+static int copy_f(lb_lattice *h, void *host_or_dev, size_t bytes, int where, bool to_lattice)
+{
+    if (int rc = check(h)) return rc;
+    const size_t want = (size_t)kQ * h->n * h->esize;
+    if (bytes != want) return fail(LB_EINVAL, "buffer is %zu bytes, expected %zu", bytes, want);
+    if (!host_or_dev) return fail(LB_EINVAL, "NULL buffer");
+    if (where != LB_HOST && where != LB_DEVICE) return fail(LB_EINVAL, "where must be LB_HOST or LB_DEVICE");
+    const size_t pl = h->n * h->esize;
+    char *state = reinterpret_cast<char *>(h->buf[h->cur]);
+    char *user = reinterpret_cast<char *>(host_or_dev);
+    hipMemcpyKind kind = where == LB_HOST ? (to_lattice ? hipMemcpyHostToDevice : hipMemcpyDeviceToHost)
+                                          : hipMemcpyDeviceToDevice;
+    for (int i = 0; i < kQ; ++i) {
+        char *lat = state + (size_t)i * h->plane * h->esize;
+        char *usr = user + (size_t)i * pl;
+        HIP_OR_FAIL(hipMemcpyAsync(to_lattice ? lat : usr, to_lattice ? usr : lat, pl, kind, h->stream));
+    }
+    if (where == LB_HOST) HIP_OR_FAIL(hipStreamSynchronize(h->stream));
+    return LB_OK;
+}
+
+int lb_get_f(lb_lattice *h, void *buf, size_t bytes, int where) { return copy_f(h, buf, bytes, where, false); }
+
+int lb_set_f(lb_lattice *h, const void *buf, size_t bytes, int where)
+{
+    return copy_f(h, const_cast<void *>(buf), bytes, where, true);
+}
+
+int lb_sync(lb_lattice *h)
+{
+    if (int rc = check(h)) return rc;
+    HIP_OR_FAIL(hipStreamSynchronize(h->stream));
+    return LB_OK;
+}
+
+long long lb_steps_done(const lb_lattice *h)
+{
+    if (!h || h->magic != kMagic) return -1;
+    return h->steps;
+}
+
+long long lb_query(const lb_lattice *h, int key)
+{
+    if (!h || h->magic != kMagic) return -1;
+    switch (key) {
+        case 0: return h->variant;
+        case 1: return h->vsites;
+        case 2: return h->solids ? 1 : 0;
+        case 3: return h->esize;
+        case 4: return h->grid;
+        case 5: return (long long)h->plane;
+        case 6: return (long long)h->n_fluid;
+        default: return -1;
+    }
+}
+
+int lb_time_steps(lb_lattice *h, int n, double *ms)
+{
+    if (int rc = check(h)) return rc;
+    if (n < 1 || !ms) return fail(LB_EINVAL, "n must be >= 1 and ms non-NULL");
+    hipEvent_t e0, e1;
+    HIP_OR_FAIL(hipEventCreate(&e0));
+    HIP_OR_FAIL(hipEventCreate(&e1));
+    int rc = LB_OK;
+    if (hipEventRecord(e0, h->stream) != hipSuccess) rc = fail(LB_EHIP, "hipEventRecord");
+    if (rc == LB_OK) rc = enqueue_steps(h, n, nullptr, nullptr);
+    if (rc == LB_OK && hipEventRecord(e1, h->stream) != hipSuccess) rc = fail(LB_EHIP, "hipEventRecord");
+    if (rc == LB_OK && hipEventSynchronize(e1) != hipSuccess) rc = fail(LB_EHIP, "hipEventSynchronize");
+    float t = 0.0f;
+    if (rc == LB_OK && hipEventElapsedTime(&t, e0, e1) != hipSuccess) rc = fail(LB_EHIP, "hipEventElapsedTime");
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc == LB_OK) *ms = t;
+    return rc;
+}
+
+int lb_copy_probe(lb_lattice *h, int reps, double *ms)
+{
+    if (int rc = check(h)) return rc;
+    if (reps < 1 || !ms) return fail(LB_EINVAL, "reps must be >= 1 and ms non-NULL");
+    const uint64_t bytes = ((uint64_t)kQ * h->plane * h->esize) & ~(uint64_t)15;
+    const int grid = h->cus * 8;
+    hipEvent_t e0, e1;
+    HIP_OR_FAIL(hipEventCreate(&e0));
+    HIP_OR_FAIL(hipEventCreate(&e1));
+    int rc = LB_OK;
+    if (launch_copy(h->buf[h->cur], h->buf[h->cur ^ 1], bytes, grid, h->stream) != hipSuccess)  // warm-up
+        rc = fail(LB_EHIP, "copy kernel launch");
+    if (rc == LB_OK && hipEventRecord(e0, h->stream) != hipSuccess) rc = fail(LB_EHIP, "hipEventRecord");
+    for (int r = 0; r < reps && rc == LB_OK; ++r)
+        if (launch_copy(h->buf[h->cur], h->buf[h->cur ^ 1], bytes, grid, h->stream) != hipSuccess)
+            rc = fail(LB_EHIP, "copy kernel launch");
+    if (rc == LB_OK && hipEventRecord(e1, h->stream) != hipSuccess) rc = fail(LB_EHIP, "hipEventRecord");
+    if (rc == LB_OK && hipEventSynchronize(e1) != hipSuccess) rc = fail(LB_EHIP, "hipEventSynchronize");
+    float t = 0.0f;
+    if (rc == LB_OK && hipEventElapsedTime(&t, e0, e1) != hipSuccess) rc = fail(LB_EHIP, "hipEventElapsedTime");
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc == LB_OK) *ms = t / reps;
+    return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,898 @@
+// D3Q19 BGK fused stream-and-collide kernels for gfx950 (CDNA4).
+//
+// Method: the lattice Boltzmann equation (paper Eq. 1) with the second-order
+// equilibrium (Eq. 2-3, sound speed squared 1/3), fused as in Section 3.1:
+// every site gathers its populations from the neighbours' stored
+// post-collision values (pull streaming), relaxes them, and writes the result
+// into the other array.  Added on top of the paper's D2Q9 scheme: the D3Q19
+// velocity set, halfway bounce-back at solid sites, periodic faces and Guo's
+// body-force source term.
+//
+// Storage: structure of arrays (Section 3.1), population i of site s at
+// plane_base + i * plane + s, s = x + nx (y + ny z).  What is stored is
+// g_i = f_i - w_i (populations shifted by their weights) in FP32, FP16 or
+// BF16; all arithmetic is FP32 (Section 3.1.1, "Mixed1").  Summing the
+// shifted values gives the density deviation rho - 1 and, because
+// sum_i w_i c_i = 0, the momentum directly.
+//
+// The update is bound by HBM bandwidth (Section 5.3 finds the paper's kernel
+// memory-bound on every device), so the kernels are built around the memory
+// stream: 16-byte loads and stores per lane and plane, lanes along x, the
+// +-1 x-shift of the pulled rows exchanged between neighbouring lanes with
+// one DPP move, no matrix cores.
+#include "lb_internal.h"
+
+namespace lbm {
+namespace {
+
+// ---------------------------------------------------------------- lattice --
+
+constexpr int CX[kQ] = {0, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1, 0, 0, 0, 0};
+constexpr int CY[kQ] = {0, 0, 0, 1, -1, 0, 0, 1, -1, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1};
+constexpr int CZ[kQ] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1};
+constexpr int OPP[kQ] = {0, 2, 1, 4, 3, 6, 5, 10, 9, 8, 7, 14, 13, 12, 11, 18, 17, 16, 15};
+constexpr float W0 = 1.0f / 3.0f, W1 = 1.0f / 18.0f, W2 = 1.0f / 36.0f;
+
+__host__ __device__ constexpr int weight_class(int i) { return i == 0 ? 0 : (i < 7 ? 1 : 2); }
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+// NW consecutive dwords of one population plane held by one lane.
+template <int NW>
+struct Lane {
+    uint32_t w[NW];
+};
+
+#ifndef LB_NT_LOAD
+#define LB_NT_LOAD 0
+#endif
+#ifndef LB_NT_STORE
+#define LB_NT_STORE 1
+#endif
+
+__device__ __forceinline__ u32x4 ld16(const void *p)
+{
+#if LB_NT_LOAD
+    return __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
+#else
+    return *reinterpret_cast<const u32x4 *>(p);
+#endif
+}
+
+__device__ __forceinline__ void st16(void *p, u32x4 v)
+{
+#if LB_NT_STORE
+    __builtin_nontemporal_store(v, reinterpret_cast<u32x4 *>(p));
+#else
+    *reinterpret_cast<u32x4 *>(p) = v;
+#endif
+}
+
+template <int NW>
+__device__ __forceinline__ Lane<NW> ldv(const char *p)
+{
+    Lane<NW> r;
+    if constexpr (NW == 4) {
+        const u32x4 v = ld16(p);
+        r.w[0] = v[0];
+        r.w[1] = v[1];
+        r.w[2] = v[2];
+        r.w[3] = v[3];
+    } else if constexpr (NW == 2) {
+#if LB_NT_LOAD
+        const u32x2 v = __builtin_nontemporal_load(reinterpret_cast<const u32x2 *>(p));
+#else
+        const u32x2 v = *reinterpret_cast<const u32x2 *>(p);
+#endif
+        r.w[0] = v[0];
+        r.w[1] = v[1];
+    } else {
+        r.w[0] = *reinterpret_cast<const uint32_t *>(p);
+    }
+    return r;
+}
+
+template <int NW>
+__device__ __forceinline__ void stv(char *p, const Lane<NW> &d)
+{
+    if constexpr (NW == 4) {
+        u32x4 v;
+        v[0] = d.w[0];
+        v[1] = d.w[1];
+        v[2] = d.w[2];
+        v[3] = d.w[3];
+        st16(p, v);
+    } else if constexpr (NW == 2) {
+        u32x2 v;
+        v[0] = d.w[0];
+        v[1] = d.w[1];
+#if LB_NT_STORE
+        __builtin_nontemporal_store(v, reinterpret_cast<u32x2 *>(p));
+#else
+        *reinterpret_cast<u32x2 *>(p) = v;
+#endif
+    } else {
+#if LB_NT_STORE
+        __builtin_nontemporal_store(d.w[0], reinterpret_cast<uint32_t *>(p));
+#else
+        *reinterpret_cast<uint32_t *>(p) = d.w[0];
+#endif
+    }
+}
+
+__device__ __forceinline__ uint32_t fastdiv(uint32_t n, const FastDiv &f)
+{
+    uint32_t t = __umulhi(n, f.m);
+    return (uint32_t)(((uint64_t)t + n) >> f.l);
+}
+
+// ----------------------------------------------------------------- codecs --
+// Each codec maps one stored element (its raw bits, zero-extended to 32 bits)
+// to float and back.  Encoding rounds to nearest, ties to even.
+
+template <int C>
+struct Codec;
+
+template <>
+struct Codec<kF32> {
+    static constexpr int kBytes = 4;
+    __device__ static float dec(uint32_t b) { return __builtin_bit_cast(float, b); }
+    __device__ static uint32_t enc(float v) { return __builtin_bit_cast(uint32_t, v); }
+    __device__ static uint32_t enc64(double v) { return __builtin_bit_cast(uint32_t, (float)v); }
+};
+
+template <>
+struct Codec<kF16> {
+    static constexpr int kBytes = 2;
+    __device__ static float dec(uint32_t b) { return (float)__builtin_bit_cast(_Float16, (uint16_t)b); }
+    __device__ static uint32_t enc(float v) { return __builtin_bit_cast(uint16_t, (_Float16)v); }
+    __device__ static uint32_t enc64(double v) { return __builtin_bit_cast(uint16_t, (_Float16)v); }
+};
+
+template <>
+struct Codec<kBF16> {
+    static constexpr int kBytes = 2;
+    __device__ static float dec(uint32_t b) { return __builtin_bit_cast(float, b << 16); }
+    __device__ static uint32_t enc(float v)
+    {
+        uint32_t u = __builtin_bit_cast(uint32_t, v);
+        if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0u;  // NaN stays a quiet NaN
+        u += 0x7fffu + ((u >> 16) & 1u);
+        return u >> 16;
+    }
+    // Nearest bfloat16 to a double (one rounding): pick among the neighbours of
+    // the float-rounded candidate.
+    __device__ static uint32_t enc64(double v)
+    {
+        uint32_t b = enc((float)v);
+        uint32_t best = b;
+        double err = fabs((double)dec(b) - v);
+        for (int k = -1; k <= 1; k += 2) {
+            uint32_t c = (b + k) & 0xffffu;
+            double e = fabs((double)dec(c) - v);
+            if (e < err || (e == err && (c & 1u) == 0)) {
+                best = c;
+                err = e;
+            }
+        }
+        return best;
+    }
+};
+
+// Element e of a lane vector, as raw bits.
+template <int C, int NW>
+__device__ __forceinline__ uint32_t vget(const Lane<NW> &d, int e)
+{
+    if constexpr (Codec<C>::kBytes == 4) {
+        return d.w[e];
+    } else {
+        return (e & 1) ? (d.w[e >> 1] >> 16) : (d.w[e >> 1] & 0xffffu);
+    }
+}
+
+template <int C, int NW>
+__device__ __forceinline__ void vset(Lane<NW> &d, int e, uint32_t b)
+{
+    if constexpr (Codec<C>::kBytes == 4) {
+        d.w[e] = b;
+    } else {
+        d.w[e >> 1] = (e & 1) ? ((d.w[e >> 1] & 0xffffu) | (b << 16)) : ((d.w[e >> 1] & 0xffff0000u) | b);
+    }
+}
+
+template <int C>
+__device__ __forceinline__ uint32_t ld_elem(const char *plane_base, uint32_t idx)
+{
+    if constexpr (Codec<C>::kBytes == 4)
+        return *reinterpret_cast<const uint32_t *>(plane_base + (size_t)idx * 4);
+    else
+        return *reinterpret_cast<const uint16_t *>(plane_base + (size_t)idx * 2);
+}
+
+template <int C>
+__device__ __forceinline__ void st_elem(char *plane_base, uint32_t idx, uint32_t b)
+{
+    if constexpr (Codec<C>::kBytes == 4)
+        *reinterpret_cast<uint32_t *>(plane_base + (size_t)idx * 4) = b;
+    else
+        *reinterpret_cast<uint16_t *>(plane_base + (size_t)idx * 2) = (uint16_t)b;
+}
+
+// -------------------------------------------------------------- collision --
+// BGK relaxation with Guo forcing on shifted populations g_i = f_i - w_i:
+//   rho = 1 + sum g,  u = (sum c g + F/2) / rho,
+//   g_i' = g_i + omega (g_i^eq - g_i) + S_i,
+//   g_i^eq = w_i [drho + rho (3 cu + 9/2 cu^2 - 3/2 u.u)],
+//   S_i = (1 - omega/2) w_i [3 c_i.F - 3 u.F + 9 cu (c_i.F)],  cu = c_i.u.
+// Directions i and opp(i) share the even part (cu^2 terms) and have opposite
+// odd parts, so each pair costs one set of coefficients:
+//   A = omega * even + S_even,  B = omega * odd + S_odd,
+//   g_i' = (1 - omega) g_i + A + B,  g_opp' = (1 - omega) g_opp + A - B.
+
+struct Coll {
+    float om, om1;
+    float fx, fy, fz, hfx, hfy, hfz;
+    float g[3];   // (1 - omega/2) w_k per weight class
+    float C[kQ];  // 9 g_k (c_i.F)   (used for the first member of each pair)
+    float D[kQ];  // 3 g_k (c_i.F)
+};
+
+__device__ __forceinline__ Coll make_coll(float omega, float fx, float fy, float fz)
+{
+    Coll p;
+    p.om = omega;
+    p.om1 = 1.0f - omega;
+    p.fx = fx;
+    p.fy = fy;
+    p.fz = fz;
+    p.hfx = 0.5f * fx;
+    p.hfy = 0.5f * fy;
+    p.hfz = 0.5f * fz;
+    const float k = 1.0f - 0.5f * omega;
+    p.g[0] = k * W0;
+    p.g[1] = k * W1;
+    p.g[2] = k * W2;
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+        const float cF = CX[i] * fx + CY[i] * fy + CZ[i] * fz;
+        p.C[i] = 9.0f * p.g[weight_class(i)] * cF;
+        p.D[i] = 3.0f * p.g[weight_class(i)] * cF;
+    }
+    return p;
+}
+
+__device__ __forceinline__ void relax_pair(float &gi, float &gj, float cu, float base, float q, float a, float C,
+                                           float D, float om1)
+{
+    const float A = base + cu * (q * cu + C);
+    const float B = a * cu + D;
+    gi = om1 * gi + (A + B);
+    gj = om1 * gj + (A - B);
+}
+
+// In: g[19] gathered pre-collision values.  Out: g[19] post-collision values,
+// rho, u (pre-collision moments with the half-force shift).
+__device__ __forceinline__ void collide(float (&g)[kQ], const Coll &p, float &rho, float &ux, float &uy, float &uz)
+{
+    const float s1 = g[1] + g[2], d1 = g[1] - g[2];
+    const float s3 = g[3] + g[4], d3 = g[3] - g[4];
+    const float s5 = g[5] + g[6], d5 = g[5] - g[6];
+    const float s7 = g[7] + g[10], d7 = g[7] - g[10];
+    const float s8 = g[8] + g[9], d8 = g[8] - g[9];
+    const float s11 = g[11] + g[14], d11 = g[11] - g[14];
+    const float s12 = g[12] + g[13], d12 = g[12] - g[13];
+    const float s15 = g[15] + g[18], d15 = g[15] - g[18];
+    const float s16 = g[16] + g[17], d16 = g[16] - g[17];
+    const float drho = g[0] + ((s1 + s3) + (s5 + s7)) + ((s8 + s11) + (s12 + s15)) + s16;
+    const float mx = d1 + d7 + d8 + d11 + d12;
+    const float my = d3 + d7 - d8 + d15 + d16;
+    const float mz = d5 + d11 - d12 + d15 - d16;
+    rho = 1.0f + drho;
+    const float inv = 1.0f / rho;
+    ux = (mx + p.hfx) * inv;
+    uy = (my + p.hfy) * inv;
+    uz = (mz + p.hfz) * inv;
+    const float uu = ux * ux + uy * uy + uz * uz;
+    const float uF = ux * p.fx + uy * p.fy + uz * p.fz;
+    const float t = drho - 1.5f * rho * uu;
+    const float base0 = p.om * W0 * t - 3.0f * p.g[0] * uF;
+    const float base1 = p.om * W1 * t - 3.0f * p.g[1] * uF;
+    const float base2 = p.om * W2 * t - 3.0f * p.g[2] * uF;
+    const float q1 = 4.5f * p.om * W1 * rho, q2 = 4.5f * p.om * W2 * rho;
+    const float a1 = 3.0f * p.om * W1 * rho, a2 = 3.0f * p.om * W2 * rho;
+    g[0] = p.om1 * g[0] + base0;
+    relax_pair(g[1], g[2], ux, base1, q1, a1, p.C[1], p.D[1], p.om1);
+    relax_pair(g[3], g[4], uy, base1, q1, a1, p.C[3], p.D[3], p.om1);
+    relax_pair(g[5], g[6], uz, base1, q1, a1, p.C[5], p.D[5], p.om1);
+    relax_pair(g[7], g[10], ux + uy, base2, q2, a2, p.C[7], p.D[7], p.om1);
+    relax_pair(g[8], g[9], ux - uy, base2, q2, a2, p.C[8], p.D[8], p.om1);
+    relax_pair(g[11], g[14], ux + uz, base2, q2, a2, p.C[11], p.D[11], p.om1);
+    relax_pair(g[12], g[13], ux - uz, base2, q2, a2, p.C[12], p.D[12], p.om1);
+    relax_pair(g[15], g[18], uy + uz, base2, q2, a2, p.C[15], p.D[15], p.om1);
+    relax_pair(g[16], g[17], uy - uz, base2, q2, a2, p.C[16], p.D[16], p.om1);
+}
+
+// Per-direction totals -> {mass deviation, momentum} of a group of sites.
+__device__ __forceinline__ void moments_of_totals(const float (&t)[kQ], float &m, float &px, float &py, float &pz)
+{
+    m = t[0] + ((t[1] + t[2]) + (t[3] + t[4])) + ((t[5] + t[6]) + (t[7] + t[8])) + ((t[9] + t[10]) + (t[11] + t[12])) +
+        ((t[13] + t[14]) + (t[15] + t[16])) + (t[17] + t[18]);
+    px = (t[1] - t[2]) + (t[7] + t[8]) - (t[9] + t[10]) + (t[11] + t[12]) - (t[13] + t[14]);
+    py = (t[3] - t[4]) + (t[7] - t[8]) + (t[9] - t[10]) + (t[15] + t[16]) - (t[17] + t[18]);
+    pz = (t[5] - t[6]) + (t[11] - t[12]) + (t[13] - t[14]) + (t[15] - t[16]) + (t[17] - t[18]);
+}
+
+// ------------------------------------------------- FP64 totals per launch --
+// Every workgroup reduces its threads' FP64 totals (wave butterfly, then LDS
+// in wave order) into partials[blockIdx.x]; the last workgroup to arrive sums
+// all partials in workgroup order and appends the result to the ring.  The
+// order of every addition is fixed, so the totals are bitwise reproducible.
+
+__device__ __forceinline__ void finish_totals(double (&acc)[4], const StepArgs &a)
+{
+    __shared__ double red[4][kBlock / 64];
+    __shared__ int is_last;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) acc[k] += __shfl_xor(acc[k], off, 64);
+    }
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) red[k][wave] = acc[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            double s = 0.0;
+            for (int w = 0; w < kBlock / 64; ++w) s += red[k][w];
+            __hip_atomic_store(&a.partials[4 * blockIdx.x + k], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __threadfence();
+        const unsigned int prev = atomicAdd(a.ticket, 1u);
+        is_last = (prev == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!is_last) return;
+    __threadfence();
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += kBlock) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            s[k] += __hip_atomic_load(&a.partials[4 * b + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __shared__ double tot[4][kBlock];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) tot[k][threadIdx.x] = s[k];
+    __syncthreads();
+    for (int w = kBlock / 2; w >= 1; w >>= 1) {
+        if (threadIdx.x < w) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) tot[k][threadIdx.x] += tot[k][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const unsigned long long step =
+            __hip_atomic_load(a.step_counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        double *r = a.ring + 4 * (step % kRingCap);
+        r[0] = a.n_fluid + tot[0][0];
+        r[1] = tot[1][0];
+        r[2] = tot[2][0];
+        r[3] = tot[3][0];
+        __hip_atomic_store(a.step_counter, step + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(a.ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// ------------------------------------------------ step: vector-row kernel --
+// A lane owns V = 16 / bytes consecutive sites of one x-row (nx % V == 0) and
+// moves one 16-byte vector per population plane in each direction.  Lanes of
+// a wave take consecutive vectors.  For c_x = 0 the pulled vector is the
+// aligned one of the source row (y - c_y, z - c_z).  For c_x = +1 (-1) the
+// source is shifted by one element: the lane loads the aligned vector and
+// takes the missing element from the previous (next) lane's vector with one
+// DPP wave shift; the lane at a row end or wave edge loads that element
+// directly, wrapping periodically in x.
+
+template <int C, int NW>
+__device__ __forceinline__ Lane<NW> shift_in_from_left(const Lane<NW> &d, uint32_t prev_elem)
+{
+    Lane<NW> r;
+    if constexpr (Codec<C>::kBytes == 4) {
+        r.w[0] = prev_elem;
+#pragma unroll
+        for (int j = 1; j < NW; ++j) r.w[j] = d.w[j - 1];
+    } else {
+        r.w[0] = (d.w[0] << 16) | prev_elem;
+#pragma unroll
+        for (int j = 1; j < NW; ++j) r.w[j] = __builtin_amdgcn_alignbyte(d.w[j], d.w[j - 1], 2);
+    }
+    return r;
+}
+
+template <int C, int NW>
+__device__ __forceinline__ Lane<NW> shift_in_from_right(const Lane<NW> &d, uint32_t next_elem)
+{
+    Lane<NW> r;
+    if constexpr (Codec<C>::kBytes == 4) {
+#pragma unroll
+        for (int j = 0; j < NW - 1; ++j) r.w[j] = d.w[j + 1];
+        r.w[NW - 1] = next_elem;
+    } else {
+#pragma unroll
+        for (int j = 0; j < NW - 1; ++j) r.w[j] = __builtin_amdgcn_alignbyte(d.w[j + 1], d.w[j], 2);
+        r.w[NW - 1] = (next_elem << 16) | (d.w[NW - 1] >> 16);
+    }
+    return r;
+}
+
+// DPP wave shifts: lane l receives lane l-1 (shr) or lane l+1 (shl).
+__device__ __forceinline__ uint32_t wave_shr1(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x138, 0xf, 0xf, false);
+}
+__device__ __forceinline__ uint32_t wave_shl1(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x130, 0xf, 0xf, false);
+}
+
+template <int V>
+__device__ __forceinline__ void store_floats(float *p, const float (&v)[V])
+{
+    if constexpr (V % 4 == 0) {
+#pragma unroll
+        for (int h = 0; h < V / 4; ++h)
+            *reinterpret_cast<float4 *>(p + 4 * h) = make_float4(v[4 * h], v[4 * h + 1], v[4 * h + 2], v[4 * h + 3]);
+    } else if constexpr (V == 2) {
+        *reinterpret_cast<float2 *>(p) = make_float2(v[0], v[1]);
+    } else {
+#pragma unroll
+        for (int e = 0; e < V; ++e) p[e] = v[e];
+    }
+}
+
+template <int V>
+__device__ __forceinline__ void load_masks(const uint32_t *p, uint32_t (&m)[V])
+{
+    if constexpr (V % 4 == 0) {
+#pragma unroll
+        for (int h = 0; h < V / 4; ++h) {
+            const u32x4 v = *reinterpret_cast<const u32x4 *>(p + 4 * h);
+            m[4 * h + 0] = v[0];
+            m[4 * h + 1] = v[1];
+            m[4 * h + 2] = v[2];
+            m[4 * h + 3] = v[3];
+        }
+    } else if constexpr (V == 2) {
+        const u32x2 v = *reinterpret_cast<const u32x2 *>(p);
+        m[0] = v[0];
+        m[1] = v[1];
+    } else {
+#pragma unroll
+        for (int e = 0; e < V; ++e) m[e] = p[e];
+    }
+}
+
+// NW: dwords per lane and plane (16-, 8- or 4-byte accesses).
+template <int C, int NW, bool kSolids, bool kMacros>
+__global__ __launch_bounds__(kBlock) void step_vec(StepArgs a)
+{
+    using K = Codec<C>;
+    constexpr int V = NW * 4 / K::kBytes;  // sites per lane
+    const Coll cp = make_coll(a.omega, a.fx, a.fy, a.fz);
+    const uint32_t nx = (uint32_t)a.nx, ny = (uint32_t)a.ny, nz = (uint32_t)a.nz;
+    const uint64_t pb = a.plane * K::kBytes;  // plane stride in bytes
+    const char *src = reinterpret_cast<const char *>(a.src);
+    char *dst = reinterpret_cast<char *>(a.dst);
+    const int lane = threadIdx.x & 63;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const int ntiles = (a.nslots + kBlock - 1) / kBlock;
+
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int slot = tile * kBlock + (int)threadIdx.x;
+        const bool active = slot < a.nslots;
+        const uint32_t s0 = (uint32_t)(active ? slot : a.nslots - 1) * V;
+        const uint32_t row = fastdiv(s0, a.div_nx);
+        const uint32_t x0 = s0 - row * nx;
+        const uint32_t z = fastdiv(row, a.div_ny);
+        const uint32_t y = row - z * ny;
+        const uint32_t ym = (y == 0 ? ny : y) - 1, yp = (y + 1 == ny) ? 0 : y + 1;
+        const uint32_t zm = (z == 0 ? nz : z) - 1, zp = (z + 1 == nz) ? 0 : z + 1;
+
+        // first element of each pulled source row
+        uint32_t rb[kQ];
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) {
+            const uint32_t ys = CY[i] > 0 ? ym : (CY[i] < 0 ? yp : y);
+            const uint32_t zs = CZ[i] > 0 ? zm : (CZ[i] < 0 ? zp : z);
+            rb[i] = (zs * ny + ys) * nx;
+        }
+
+        Lane<NW> d[kQ];
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) d[i] = ldv<NW>(src + i * pb + (size_t)(rb[i] + x0) * K::kBytes);
+
+        // +-1 shifts along x (all lanes take part in the DPP moves)
+        const bool left_edge = (lane == 0) || (x0 == 0);
+        const bool right_edge = (lane == 63) || (x0 + V == nx);
+        const uint32_t xl = (x0 == 0 ? nx : x0) - 1;
+        const uint32_t xr = (x0 + V == nx) ? 0 : x0 + V;
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) {
+            if (CX[i] == 1) {
+                uint32_t prev = wave_shr1(d[i].w[NW - 1]);
+                if constexpr (K::kBytes == 2) prev >>= 16;
+                if (left_edge) prev = ld_elem<C>(src + i * pb, rb[i] + xl);
+                d[i] = shift_in_from_left<C, NW>(d[i], prev);
+            } else if (CX[i] == -1) {
+                uint32_t next = wave_shl1(d[i].w[0]);
+                if constexpr (K::kBytes == 2) next &= 0xffffu;
+                if (right_edge) next = ld_elem<C>(src + i * pb, rb[i] + xr);
+                d[i] = shift_in_from_right<C, NW>(d[i], next);
+            }
+        }
+
+        // halfway bounce-back: where x - c_i is solid, take the site's own opp(i) value
+        uint32_t own_solid = 0;  // bit e: site e of this lane is solid
+        if constexpr (kSolids) {
+            if (a.rowdirty[row]) {
+                uint32_t m[V];
+                load_masks<V>(a.nbmask + s0, m);
+#pragma unroll
+                for (int e = 0; e < V; ++e) own_solid |= (m[e] >> 31) << e;
+#pragma unroll
+                for (int i = 1; i < kQ; ++i) {
+                    uint32_t sel = 0;  // bit e set: element e bounces back
+#pragma unroll
+                    for (int e = 0; e < V; ++e) sel |= ((m[e] >> i) & 1u) << e;
+                    if (sel) {
+                        const Lane<NW> o = ldv<NW>(src + OPP[i] * pb + (size_t)s0 * K::kBytes);
+#pragma unroll
+                        for (int e = 0; e < V; ++e)
+                            if ((sel >> e) & 1u) vset<C, NW>(d[i], e, vget<C, NW>(o, e));
+                    }
+                }
+            }
+        }
+
+        // collide site by site
+        float mr[V], mu[V], mv[V], mw[V];
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            float g[kQ];
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) g[i] = K::dec(vget<C, NW>(d[i], e));
+            float rho, ux, uy, uz;
+            collide(g, cp, rho, ux, uy, uz);
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) vset<C, NW>(d[i], e, K::enc(g[i]));
+            const bool fluid = !((own_solid >> e) & 1u);
+            mr[e] = fluid ? rho : 0.0f;
+            mu[e] = fluid ? ux : 0.0f;
+            mv[e] = fluid ? uy : 0.0f;
+            mw[e] = fluid ? uz : 0.0f;
+        }
+
+        if (active) {
+            if (own_solid == 0) {
+#pragma unroll
+                for (int i = 0; i < kQ; ++i) stv<NW>(dst + i * pb + (size_t)s0 * K::kBytes, d[i]);
+            } else if (own_solid != (1u << V) - 1u) {
+#pragma unroll
+                for (int i = 0; i < kQ; ++i)
+#pragma unroll
+                    for (int e = 0; e < V; ++e)
+                        if (!((own_solid >> e) & 1u)) st_elem<C>(dst + i * pb, s0 + e, vget<C, NW>(d[i], e));
+            }
+            if constexpr (kMacros) {
+                const size_t n = (size_t)nx * ny * nz;
+                store_floats<V>(a.rho_out + s0, mr);
+                store_floats<V>(a.u_out + s0, mu);
+                store_floats<V>(a.u_out + n + s0, mv);
+                store_floats<V>(a.u_out + 2 * n + s0, mw);
+            }
+            // totals of the values as stored (after rounding), fluid sites only
+            float tot[kQ];
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) {
+                float t = 0.0f;
+#pragma unroll
+                for (int e = 0; e < V; ++e)
+                    if (!((own_solid >> e) & 1u)) t += K::dec(vget<C, NW>(d[i], e));
+                tot[i] = t;
+            }
+            float m, px, py, pz;
+            moments_of_totals(tot, m, px, py, pz);
+            acc[0] += (double)m;
+            acc[1] += (double)px;
+            acc[2] += (double)py;
+            acc[3] += (double)pz;
+        }
+    }
+    finish_totals(acc, a);
+}
+
+// ---------------------------------------------- step: one site per thread --
+// General fallback for any nx: each lane gathers its 19 values with its own
+// periodic wrap, no lane exchange.
+
+template <int C, bool kSolids, bool kMacros>
+__global__ __launch_bounds__(kBlock) void step_site(StepArgs a)
+{
+    using K = Codec<C>;
+    const Coll cp = make_coll(a.omega, a.fx, a.fy, a.fz);
+    const uint32_t nx = (uint32_t)a.nx, ny = (uint32_t)a.ny, nz = (uint32_t)a.nz;
+    const uint64_t pb = a.plane * K::kBytes;
+    const char *src = reinterpret_cast<const char *>(a.src);
+    char *dst = reinterpret_cast<char *>(a.dst);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const int ntiles = (a.nslots + kBlock - 1) / kBlock;
+
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int slot = tile * kBlock + (int)threadIdx.x;
+        if (slot >= a.nslots) continue;
+        const uint32_t s = (uint32_t)slot;
+        const uint32_t row = fastdiv(s, a.div_nx);
+        const uint32_t x = s - row * nx;
+        const uint32_t z = fastdiv(row, a.div_ny);
+        const uint32_t y = row - z * ny;
+        uint32_t mask = 0;
+        if constexpr (kSolids) {
+            if (a.rowdirty[row]) mask = a.nbmask[s];
+            if (mask >> 31) continue;  // solid site: not part of the state
+        }
+        const uint32_t xm = (x == 0 ? nx : x) - 1, xp = (x + 1 == nx) ? 0 : x + 1;
+        const uint32_t ym = (y == 0 ? ny : y) - 1, yp = (y + 1 == ny) ? 0 : y + 1;
+        const uint32_t zm = (z == 0 ? nz : z) - 1, zp = (z + 1 == nz) ? 0 : z + 1;
+        float g[kQ];
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) {
+            const uint32_t xs = CX[i] > 0 ? xm : (CX[i] < 0 ? xp : x);
+            const uint32_t ys = CY[i] > 0 ? ym : (CY[i] < 0 ? yp : y);
+            const uint32_t zs = CZ[i] > 0 ? zm : (CZ[i] < 0 ? zp : z);
+            uint32_t b;
+            if (kSolids && ((mask >> i) & 1u))
+                b = ld_elem<C>(src + OPP[i] * pb, s);
+            else
+                b = ld_elem<C>(src + i * pb, (zs * ny + ys) * nx + xs);
+            g[i] = K::dec(b);
+        }
+        float rho, ux, uy, uz;
+        collide(g, cp, rho, ux, uy, uz);
+        float tot[kQ];
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) {
+            const uint32_t b = K::enc(g[i]);
+            st_elem<C>(dst + i * pb, s, b);
+            tot[i] = K::dec(b);
+        }
+        if constexpr (kMacros) {
+            const size_t n = (size_t)nx * ny * nz;
+            a.rho_out[s] = rho;
+            a.u_out[s] = ux;
+            a.u_out[n + s] = uy;
+            a.u_out[2 * n + s] = uz;
+        }
+        float m, px, py, pz;
+        moments_of_totals(tot, m, px, py, pz);
+        acc[0] += (double)m;
+        acc[1] += (double)px;
+        acc[2] += (double)py;
+        acc[3] += (double)pz;
+    }
+    finish_totals(acc, a);
+}
+
+// Solid sites get zero macros in the one-site kernel (it skips them).
+__global__ __launch_bounds__(kBlock) void zero_solid_macros(const uint8_t *flags, int n, float *rho, float *u)
+{
+    for (int s = blockIdx.x * kBlock + threadIdx.x; s < n; s += gridDim.x * kBlock) {
+        if (flags[s]) {
+            rho[s] = 0.0f;
+            u[s] = 0.0f;
+            u[(size_t)n + s] = 0.0f;
+            u[2 * (size_t)n + s] = 0.0f;
+        }
+    }
+}
+
+// -------------------------------------------------------- initialisation --
+// g_i = f_i^eq(rho, u) - w_i computed in FP64 and rounded once to storage.
+
+template <int C>
+__global__ __launch_bounds__(kBlock) void init_eq(InitArgs a)
+{
+    using K = Codec<C>;
+    const uint64_t pb = a.plane * K::kBytes;
+    char *dst = reinterpret_cast<char *>(a.dst);
+    const double w[3] = {1.0 / 3.0, 1.0 / 18.0, 1.0 / 36.0};
+    for (int s = blockIdx.x * kBlock + threadIdx.x; s < a.n; s += gridDim.x * kBlock) {
+        const bool solid = a.flags && a.flags[s];
+        const double rho = a.rho ? a.rho[s] : 1.0;
+        const double ux = a.u ? a.u[s] : 0.0;
+        const double uy = a.u ? a.u[(size_t)a.n + s] : 0.0;
+        const double uz = a.u ? a.u[2 * (size_t)a.n + s] : 0.0;
+        const double drho = rho - 1.0;
+        const double uu = ux * ux + uy * uy + uz * uz;
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) {
+            const double cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
+            const double geq = w[weight_class(i)] * (drho + rho * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
+            st_elem<C>(dst + i * pb, (uint32_t)s, solid ? 0u : K::enc64(geq));
+        }
+    }
+}
+
+// ---------------------------------------------------------------- macros --
+// rho = 1 + sum g,  u = (sum c g - F/2) / rho of the stored state.
+
+template <int C>
+__global__ __launch_bounds__(kBlock) void macros_kernel(MacroArgs a)
+{
+    using K = Codec<C>;
+    const uint64_t pb = a.plane * K::kBytes;
+    const char *src = reinterpret_cast<const char *>(a.src);
+    for (int s = blockIdx.x * kBlock + threadIdx.x; s < a.n; s += gridDim.x * kBlock) {
+        float r = 0.0f, ux = 0.0f, uy = 0.0f, uz = 0.0f;
+        if (!(a.flags && a.flags[s])) {
+            float g[kQ];
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) g[i] = K::dec(ld_elem<C>(src + i * pb, (uint32_t)s));
+            float m, px, py, pz;
+            moments_of_totals(g, m, px, py, pz);
+            r = 1.0f + m;
+            const float inv = 1.0f / r;
+            ux = (px - 0.5f * a.fx) * inv;
+            uy = (py - 0.5f * a.fy) * inv;
+            uz = (pz - 0.5f * a.fz) * inv;
+        }
+        if (a.rho) a.rho[s] = r;
+        if (a.u) {
+            a.u[s] = ux;
+            a.u[(size_t)a.n + s] = uy;
+            a.u[2 * (size_t)a.n + s] = uz;
+        }
+    }
+}
+
+// ------------------------------------------------------ neighbour masks --
+// bit i (1..18): site x - c_i is solid; bit 31: the site itself is solid.
+
+__global__ __launch_bounds__(kBlock) void build_masks(const uint8_t *flags, int nx, int ny, int nz, uint32_t *nbmask)
+{
+    const int n = nx * ny * nz;
+    for (int s = blockIdx.x * kBlock + threadIdx.x; s < n; s += gridDim.x * kBlock) {
+        const int x = s % nx, y = (s / nx) % ny, z = s / (nx * ny);
+        uint32_t m = flags[s] ? (1u << 31) : 0u;
+#pragma unroll
+        for (int i = 1; i < kQ; ++i) {
+            int xs = x - CX[i], ys = y - CY[i], zs = z - CZ[i];
+            xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
+            ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
+            zs = zs < 0 ? zs + nz : (zs >= nz ? zs - nz : zs);
+            if (flags[(zs * ny + ys) * nx + xs]) m |= 1u << i;
+        }
+        nbmask[s] = m;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void build_rowdirty(const uint32_t *nbmask, int nx, int nrows, uint8_t *rowdirty)
+{
+    for (int r = blockIdx.x * kBlock + threadIdx.x; r < nrows; r += gridDim.x * kBlock) {
+        uint32_t any = 0;
+        for (int x = 0; x < nx; ++x) any |= nbmask[(size_t)r * nx + x];
+        rowdirty[r] = any ? 1 : 0;
+    }
+}
+
+// ------------------------------------------------------------ copy probe --
+
+__global__ __launch_bounds__(kBlock) void copy16(const u32x4 *src, u32x4 *dst, uint64_t n16)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n16; i += (uint64_t)gridDim.x * kBlock)
+        st16(dst + i, ld16(src + i));
+}
+
+inline int grid_for(uint64_t n, int cap = 65536)
+{
+    uint64_t g = (n + kBlock - 1) / kBlock;
+    if (g > (uint64_t)cap) g = cap;
+    return g < 1 ? 1 : (int)g;
+}
+
+template <int C, bool S, bool M>
+void *step_fn(int variant)
+{
+    if (variant == 1) return reinterpret_cast<void *>(&step_vec<C, 4, S, M>);
+    if (variant == 2) return reinterpret_cast<void *>(&step_vec<C, 2, S, M>);
+    if (variant == 3) return reinterpret_cast<void *>(&step_vec<C, 1, S, M>);
+    return reinterpret_cast<void *>(&step_site<C, S, M>);
+}
+
+void *pick_step(int codec, int variant, bool solids, bool macros)
+{
+#define LB_PICK(C)                                                                                 \
+    if (solids) return macros ? step_fn<C, true, true>(variant) : step_fn<C, true, false>(variant); \
+    return macros ? step_fn<C, false, true>(variant) : step_fn<C, false, false>(variant);
+    switch (codec) {
+        case kF32: LB_PICK(kF32)
+        case kF16: LB_PICK(kF16)
+        default: LB_PICK(kBF16)
+    }
+#undef LB_PICK
+}
+
+}  // namespace
+
+int sites_per_thread(int codec, int variant)
+{
+    const int nw = variant == 1 ? 4 : (variant == 2 ? 2 : (variant == 3 ? 1 : 0));
+    if (nw == 0) return 1;
+    return nw * 4 / (codec == kF32 ? 4 : 2);
+}
+
+int step_occupancy(int codec, int variant, bool solids, bool macros)
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pick_step(codec, variant, solids, macros), kBlock, 0) !=
+        hipSuccess)
+        return 1;
+    return nb < 1 ? 1 : nb;
+}
+
+hipError_t launch_step(int codec, int variant, bool solids, bool macros, const StepArgs &a, int grid, hipStream_t s)
+{
+    void *fn = pick_step(codec, variant, solids, macros);
+    StepArgs arg = a;
+    void *params[] = {&arg};
+    return hipLaunchKernel(fn, dim3(grid), dim3(kBlock), params, 0, s);
+}
+
+hipError_t launch_init(int codec, const InitArgs &a, hipStream_t s)
+{
+    const int g = grid_for((uint64_t)a.n);
+    switch (codec) {
+        case kF32: init_eq<kF32><<<g, kBlock, 0, s>>>(a); break;
+        case kF16: init_eq<kF16><<<g, kBlock, 0, s>>>(a); break;
+        default: init_eq<kBF16><<<g, kBlock, 0, s>>>(a); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_macros(int codec, const MacroArgs &a, hipStream_t s)
+{
+    const int g = grid_for((uint64_t)a.n);
+    switch (codec) {
+        case kF32: macros_kernel<kF32><<<g, kBlock, 0, s>>>(a); break;
+        case kF16: macros_kernel<kF16><<<g, kBlock, 0, s>>>(a); break;
+        default: macros_kernel<kBF16><<<g, kBlock, 0, s>>>(a); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_masks(const uint8_t *flags, int nx, int ny, int nz, uint32_t *nbmask, uint8_t *rowdirty,
+                        hipStream_t s)
+{
+    const int n = nx * ny * nz;
+    build_masks<<<grid_for((uint64_t)n), kBlock, 0, s>>>(flags, nx, ny, nz, nbmask);
+    build_rowdirty<<<grid_for((uint64_t)ny * nz), kBlock, 0, s>>>(nbmask, nx, ny * nz, rowdirty);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_solid_macros(const uint8_t *flags, int n, float *rho, float *u, hipStream_t s)
+{
+    zero_solid_macros<<<grid_for((uint64_t)n), kBlock, 0, s>>>(flags, n, rho, u);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(const void *src, void *dst, uint64_t bytes, int grid, hipStream_t s)
+{
+    copy16<<<grid, kBlock, 0, s>>>(reinterpret_cast<const u32x4 *>(src), reinterpret_cast<u32x4 *>(dst), bytes / 16);
+    return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -1,0 +1,84 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry point
+that include/lb.h declares, and rejects bad arguments before touching HIP."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2409_16781_amd as lbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lb.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lb_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("lb_create", "lb_step", "lb_macros", "lb_destroy", "lb_init_eq", "lb_sums",
+                     "lb_get_f", "lb_set_f", "lb_set_force", "lb_create_ex", "lb_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = lbm.lib()
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_binding_signatures_cover_the_header():
+    assert sorted(lbm._SIGNATURES) == declared_functions()
+
+
+@pytest.mark.parametrize("args,needle", [
+    ((0, 4, 4, 0.8), "extents"),
+    ((4, -1, 4, 0.8), "extents"),
+    ((4, 4, 4, 0.5), "tau"),
+    ((4, 4, 4, 0.3), "tau"),
+    ((4, 4, 4, float("nan")), "tau"),
+    ((1 << 11, 1 << 10, 1 << 10, 0.8), "exceeds"),
+])
+def test_create_rejects_bad_arguments(args, needle):
+    L = lbm.lib()
+    h = L.lb_create(*args, None)
+    assert not h
+    assert needle in lbm.last_error()
+
+
+def test_create_rejects_bad_codec_and_flags():
+    L = lbm.lib()
+    assert not L.lb_create_ex(4, 4, 4, 0.8, None, 7, None)
+    assert "codec" in lbm.last_error()
+    flags = np.zeros(64, dtype=np.uint8)
+    flags[10] = 2
+    assert not L.lb_create(4, 4, 4, 0.8, flags.ctypes.data_as(ctypes.c_void_p))
+    assert "flag value 2" in lbm.last_error()
+
+
+def test_null_handle_is_rejected_everywhere():
+    L = lbm.lib()
+    assert L.lb_step(None, 1) == lbm.LB_ESTATE
+    assert L.lb_macros(None, None, None) == lbm.LB_ESTATE
+    assert L.lb_set_force(None, 0.0, 0.0, 0.0) == lbm.LB_ESTATE
+    assert L.lb_sync(None) == lbm.LB_ESTATE
+    assert L.lb_steps_done(None) == -1
+    assert L.lb_query(None, 0) == -1
+    L.lb_destroy(None)  # no-op
+
+
+def test_tau_infinity_is_accepted_by_validation():
+    """tau = +inf (omega = 0) passes argument checks; without a GPU the call
+    then fails on the device query, with a HIP error rather than EINVAL."""
+    L = lbm.lib()
+    h = L.lb_create(4, 4, 4, math.inf, None)
+    if h:  # a GPU is present
+        L.lb_destroy(h)
+    else:
+        assert "tau" not in lbm.last_error()
