@@ -503,16 +503,15 @@ int lb_copy_probe(lb_lattice *h, int reps, double *ms)
     if (int rc = check(h)) return rc;
     if (reps < 1 || !ms) return fail(LB_EINVAL, "reps must be >= 1 and ms non-NULL");
     const uint64_t bytes = ((uint64_t)kQ * h->plane * h->esize) & ~(uint64_t)15;
-    const int grid = h->cus * 8;
     hipEvent_t e0, e1;
     HIP_OR_FAIL(hipEventCreate(&e0));
     HIP_OR_FAIL(hipEventCreate(&e1));
     int rc = LB_OK;
-    if (launch_copy(h->buf[h->cur], h->buf[h->cur ^ 1], bytes, grid, h->stream) != hipSuccess)  // warm-up
+    if (launch_copy(h->buf[h->cur], h->buf[h->cur ^ 1], bytes, h->stream) != hipSuccess)  // warm-up
         rc = fail(LB_EHIP, "copy kernel launch");
     if (rc == LB_OK && hipEventRecord(e0, h->stream) != hipSuccess) rc = fail(LB_EHIP, "hipEventRecord");
     for (int r = 0; r < reps && rc == LB_OK; ++r)
-        if (launch_copy(h->buf[h->cur], h->buf[h->cur ^ 1], bytes, grid, h->stream) != hipSuccess)
+        if (launch_copy(h->buf[h->cur], h->buf[h->cur ^ 1], bytes, h->stream) != hipSuccess)
             rc = fail(LB_EHIP, "copy kernel launch");
     if (rc == LB_OK && hipEventRecord(e1, h->stream) != hipSuccess) rc = fail(LB_EHIP, "hipEventRecord");
     if (rc == LB_OK && hipEventSynchronize(e1) != hipSuccess) rc = fail(LB_EHIP, "hipEventSynchronize");

@@ -77,7 +77,7 @@ hipError_t launch_macros(int codec, const MacroArgs &a, hipStream_t s);
 hipError_t launch_masks(const uint8_t *flags, int nx, int ny, int nz, uint32_t *nbmask, uint8_t *rowdirty,
                         hipStream_t s);
 hipError_t launch_zero_solid_macros(const uint8_t *flags, int n, float *rho, float *u, hipStream_t s);
-hipError_t launch_copy(const void *src, void *dst, uint64_t bytes, int grid, hipStream_t s);
+hipError_t launch_copy(const void *src, void *dst, uint64_t bytes, hipStream_t s);
 int step_occupancy(int codec, int variant, bool solids, bool macros);  // workgroups per CU
 int sites_per_thread(int codec, int variant);
 

@@ -31,7 +31,7 @@ constexpr int CX[kQ] = {0, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1, 0, 0, 
 constexpr int CY[kQ] = {0, 0, 0, 1, -1, 0, 0, 1, -1, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1};
 constexpr int CZ[kQ] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1};
 constexpr int OPP[kQ] = {0, 2, 1, 4, 3, 6, 5, 10, 9, 8, 7, 14, 13, 12, 11, 18, 17, 16, 15};
-constexpr float W0 = 1.0f / 3.0f, W1 = 1.0f / 18.0f, W2 = 1.0f / 36.0f;
+constexpr float W1 = 1.0f / 18.0f, W2 = 1.0f / 36.0f;
 
 __host__ __device__ constexpr int weight_class(int i) { return i == 0 ? 0 : (i < 7 ? 1 : 2); }
 
@@ -221,28 +221,41 @@ __device__ __forceinline__ void st_elem(char *plane_base, uint32_t idx, uint32_t
 
 // -------------------------------------------------------------- collision --
 // BGK relaxation with Guo forcing on shifted populations g_i = f_i - w_i:
-//   rho = 1 + sum g,  u = (sum c g + F/2) / rho,
+//   rho = 1 + sum g,  j = sum c g + F/2 (= rho u),
 //   g_i' = g_i + omega (g_i^eq - g_i) + S_i,
-//   g_i^eq = w_i [drho + rho (3 cu + 9/2 cu^2 - 3/2 u.u)],
-//   S_i = (1 - omega/2) w_i [3 c_i.F - 3 u.F + 9 cu (c_i.F)],  cu = c_i.u.
-// Directions i and opp(i) share the even part (cu^2 terms) and have opposite
-// odd parts, so each pair costs one set of coefficients:
-//   A = omega * even + S_even,  B = omega * odd + S_odd,
-//   g_i' = (1 - omega) g_i + A + B,  g_opp' = (1 - omega) g_opp + A - B.
+//   g_i^eq = w_i [drho + 3 c_i.j + (9/2)(c_i.j)(c_i.u) - (3/2) j.u],
+//   S_i = (1 - omega/2) w_i [3 c_i.F - 3 u.F + 9 (c_i.u)(c_i.F)].
+// Directions i and opp(i) form a pair p with sum s_p = g_i + g_opp and
+// difference d_p = g_i - g_opp.  The update is applied as increments:
+//   s_p' - s_p = omega (s_p^eq - s_p) + (S_i + S_opp)          (even part)
+//   d_p' - d_p = -omega n_p + (S_i - S_opp),  n_p = d_p - d_p^eq (odd part)
+//   s_p^eq = 2 w_k (drho - 3/2 j.u) + 9 w_k (c.j)(c.u),  d_p^eq = 6 w_k c.j.
+//
+// FP32 arrangement.  The collision keeps mass and adds exactly F to the
+// momentum.  Rounding must not break those identities by a constant factor,
+// or the error grows every step (by about 1e-7 of the momentum per step).
+// So every quantity that carries mass or momentum is formed from small
+// numbers:
+//  - the odd non-equilibrium parts n_p of the six diagonal pairs are computed
+//    directly, and the three axis pairs take the remainder of
+//    sum_p c_p n_p = m - j = -F/2;
+//  - the rest population takes the remainder of the mass increments;
+//  - each population changes by g' = g + increment, rounded once.
+// With this the FP32 result stays at the rounding level of FP32 storage.
 
 struct Coll {
-    float om, om1;
-    float fx, fy, fz, hfx, hfy, hfz;
-    float g[3];   // (1 - omega/2) w_k per weight class
-    float C[kQ];  // 9 g_k (c_i.F)   (used for the first member of each pair)
-    float D[kQ];  // 3 g_k (c_i.F)
+    float hom;                // omega / 2
+    float fx, fy, fz;
+    float hfx, hfy, hfz;      // F / 2
+    float g31, g32;           // 3 (1 - omega/2) w_k      (axis, diagonal)
+    float hC[kQ];             // 9 (1 - omega/2) w_k c_i.F (first member of each pair)
+    float hD[kQ];             // 3 (1 - omega/2) w_k c_i.F
 };
 
 __device__ __forceinline__ Coll make_coll(float omega, float fx, float fy, float fz)
 {
     Coll p;
-    p.om = omega;
-    p.om1 = 1.0f - omega;
+    p.hom = 0.5f * omega;
     p.fx = fx;
     p.fy = fy;
     p.fz = fz;
@@ -250,29 +263,33 @@ __device__ __forceinline__ Coll make_coll(float omega, float fx, float fy, float
     p.hfy = 0.5f * fy;
     p.hfz = 0.5f * fz;
     const float k = 1.0f - 0.5f * omega;
-    p.g[0] = k * W0;
-    p.g[1] = k * W1;
-    p.g[2] = k * W2;
+    p.g31 = 3.0f * k * W1;
+    p.g32 = 3.0f * k * W2;
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
         const float cF = CX[i] * fx + CY[i] * fy + CZ[i] * fz;
-        p.C[i] = 9.0f * p.g[weight_class(i)] * cF;
-        p.D[i] = 3.0f * p.g[weight_class(i)] * cF;
+        const float gk = k * (weight_class(i) == 1 ? W1 : W2);
+        p.hC[i] = 9.0f * gk * cF;
+        p.hD[i] = 3.0f * gk * cF;
     }
     return p;
 }
 
-__device__ __forceinline__ void relax_pair(float &gi, float &gj, float cu, float base, float q, float a, float C,
-                                           float D, float om1)
+// Half increments of one pair (i, j): hs = (s' - s) / 2, hd = (d' - d) / 2.
+__device__ __forceinline__ void relax_pair(float &gi, float &gj, float s, float n, float cj, float inv, float ts,
+                                           float nw, float e, float hC, float hD, float hom, float &sum_hs)
 {
-    const float A = base + cu * (q * cu + C);
-    const float B = a * cu + D;
-    gi = om1 * gi + (A + B);
-    gj = om1 * gj + (A - B);
+    const float cu = cj * inv;
+    const float seq = (nw * cj) * cu + ts;
+    const float hs = hom * (seq - s) + (hC * cu - e);
+    const float hd = hD - hom * n;
+    gi = gi + (hs + hd);
+    gj = gj + (hs - hd);
+    sum_hs += hs;
 }
 
 // In: g[19] gathered pre-collision values.  Out: g[19] post-collision values,
-// rho, u (pre-collision moments with the half-force shift).
+// rho and u (pre-collision moments, u with the half-force shift).
 __device__ __forceinline__ void collide(float (&g)[kQ], const Coll &p, float &rho, float &ux, float &uy, float &uz)
 {
     const float s1 = g[1] + g[2], d1 = g[1] - g[2];
@@ -285,32 +302,42 @@ __device__ __forceinline__ void collide(float (&g)[kQ], const Coll &p, float &rh
     const float s15 = g[15] + g[18], d15 = g[15] - g[18];
     const float s16 = g[16] + g[17], d16 = g[16] - g[17];
     const float drho = g[0] + ((s1 + s3) + (s5 + s7)) + ((s8 + s11) + (s12 + s15)) + s16;
-    const float mx = d1 + d7 + d8 + d11 + d12;
-    const float my = d3 + d7 - d8 + d15 + d16;
-    const float mz = d5 + d11 - d12 + d15 - d16;
+    const float jx = (d1 + d7 + d8 + d11 + d12) + p.hfx;
+    const float jy = (d3 + d7 - d8 + d15 + d16) + p.hfy;
+    const float jz = (d5 + d11 - d12 + d15 - d16) + p.hfz;
     rho = 1.0f + drho;
     const float inv = 1.0f / rho;
-    ux = (mx + p.hfx) * inv;
-    uy = (my + p.hfy) * inv;
-    uz = (mz + p.hfz) * inv;
-    const float uu = ux * ux + uy * uy + uz * uz;
+    ux = jx * inv;
+    uy = jy * inv;
+    uz = jz * inv;
+    const float ju = jx * ux + jy * uy + jz * uz;  // rho u.u
     const float uF = ux * p.fx + uy * p.fy + uz * p.fz;
-    const float t = drho - 1.5f * rho * uu;
-    const float base0 = p.om * W0 * t - 3.0f * p.g[0] * uF;
-    const float base1 = p.om * W1 * t - 3.0f * p.g[1] * uF;
-    const float base2 = p.om * W2 * t - 3.0f * p.g[2] * uF;
-    const float q1 = 4.5f * p.om * W1 * rho, q2 = 4.5f * p.om * W2 * rho;
-    const float a1 = 3.0f * p.om * W1 * rho, a2 = 3.0f * p.om * W2 * rho;
-    g[0] = p.om1 * g[0] + base0;
-    relax_pair(g[1], g[2], ux, base1, q1, a1, p.C[1], p.D[1], p.om1);
-    relax_pair(g[3], g[4], uy, base1, q1, a1, p.C[3], p.D[3], p.om1);
-    relax_pair(g[5], g[6], uz, base1, q1, a1, p.C[5], p.D[5], p.om1);
-    relax_pair(g[7], g[10], ux + uy, base2, q2, a2, p.C[7], p.D[7], p.om1);
-    relax_pair(g[8], g[9], ux - uy, base2, q2, a2, p.C[8], p.D[8], p.om1);
-    relax_pair(g[11], g[14], ux + uz, base2, q2, a2, p.C[11], p.D[11], p.om1);
-    relax_pair(g[12], g[13], ux - uz, base2, q2, a2, p.C[12], p.D[12], p.om1);
-    relax_pair(g[15], g[18], uy + uz, base2, q2, a2, p.C[15], p.D[15], p.om1);
-    relax_pair(g[16], g[17], uy - uz, base2, q2, a2, p.C[16], p.D[16], p.om1);
+    const float t = drho - 1.5f * ju;
+    const float ts1 = (2.0f * W1) * t, ts2 = (2.0f * W2) * t;
+    const float e1 = p.g31 * uF, e2 = p.g32 * uF;
+
+    // odd non-equilibrium parts: diagonals directly, axes as the remainder
+    const float c7 = jx + jy, c8 = jx - jy, c11 = jx + jz, c12 = jx - jz, c15 = jy + jz, c16 = jy - jz;
+    constexpr float kSixth = 1.0f / 6.0f;
+    const float n7 = d7 - kSixth * c7, n8 = d8 - kSixth * c8;
+    const float n11 = d11 - kSixth * c11, n12 = d12 - kSixth * c12;
+    const float n15 = d15 - kSixth * c15, n16 = d16 - kSixth * c16;
+    const float n1 = -p.hfx - ((n7 + n8) + (n11 + n12));
+    const float n3 = -p.hfy - ((n7 - n8) + (n15 + n16));
+    const float n5 = -p.hfz - ((n11 - n12) + (n15 - n16));
+
+    constexpr float kNW1 = 9.0f * W1, kNW2 = 9.0f * W2;
+    float sum_hs = 0.0f;
+    relax_pair(g[1], g[2], s1, n1, jx, inv, ts1, kNW1, e1, p.hC[1], p.hD[1], p.hom, sum_hs);
+    relax_pair(g[3], g[4], s3, n3, jy, inv, ts1, kNW1, e1, p.hC[3], p.hD[3], p.hom, sum_hs);
+    relax_pair(g[5], g[6], s5, n5, jz, inv, ts1, kNW1, e1, p.hC[5], p.hD[5], p.hom, sum_hs);
+    relax_pair(g[7], g[10], s7, n7, c7, inv, ts2, kNW2, e2, p.hC[7], p.hD[7], p.hom, sum_hs);
+    relax_pair(g[8], g[9], s8, n8, c8, inv, ts2, kNW2, e2, p.hC[8], p.hD[8], p.hom, sum_hs);
+    relax_pair(g[11], g[14], s11, n11, c11, inv, ts2, kNW2, e2, p.hC[11], p.hD[11], p.hom, sum_hs);
+    relax_pair(g[12], g[13], s12, n12, c12, inv, ts2, kNW2, e2, p.hC[12], p.hD[12], p.hom, sum_hs);
+    relax_pair(g[15], g[18], s15, n15, c15, inv, ts2, kNW2, e2, p.hC[15], p.hD[15], p.hom, sum_hs);
+    relax_pair(g[16], g[17], s16, n16, c16, inv, ts2, kNW2, e2, p.hC[16], p.hD[16], p.hom, sum_hs);
+    g[0] = g[0] - 2.0f * sum_hs;
 }
 
 // Per-direction totals -> {mass deviation, momentum} of a group of sites.
@@ -791,10 +818,24 @@ __global__ __launch_bounds__(kBlock) void build_rowdirty(const uint32_t *nbmask,
 
 // ------------------------------------------------------------ copy probe --
 
+// Each workgroup copies one contiguous 16 KiB chunk (4 coalesced 16-byte
+// accesses per lane), the access pattern of a plain streaming copy.
+constexpr int kCopyUnroll = 4;
+
 __global__ __launch_bounds__(kBlock) void copy16(const u32x4 *src, u32x4 *dst, uint64_t n16)
 {
-    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n16; i += (uint64_t)gridDim.x * kBlock)
-        st16(dst + i, ld16(src + i));
+    const uint64_t base = (uint64_t)blockIdx.x * (kBlock * kCopyUnroll) + threadIdx.x;
+    u32x4 v[kCopyUnroll];
+#pragma unroll
+    for (int k = 0; k < kCopyUnroll; ++k) {
+        const uint64_t i = base + (uint64_t)k * kBlock;
+        if (i < n16) v[k] = ld16(src + i);
+    }
+#pragma unroll
+    for (int k = 0; k < kCopyUnroll; ++k) {
+        const uint64_t i = base + (uint64_t)k * kBlock;
+        if (i < n16) st16(dst + i, v[k]);
+    }
 }
 
 inline int grid_for(uint64_t n, int cap = 65536)
@@ -889,9 +930,13 @@ hipError_t launch_zero_solid_macros(const uint8_t *flags, int n, float *rho, flo
     return hipGetLastError();
 }
 
-hipError_t launch_copy(const void *src, void *dst, uint64_t bytes, int grid, hipStream_t s)
+hipError_t launch_copy(const void *src, void *dst, uint64_t bytes, hipStream_t s)
 {
-    copy16<<<grid, kBlock, 0, s>>>(reinterpret_cast<const u32x4 *>(src), reinterpret_cast<u32x4 *>(dst), bytes / 16);
+    const uint64_t n16 = bytes / 16;
+    const uint64_t per_block = (uint64_t)kBlock * kCopyUnroll;
+    const uint64_t grid = (n16 + per_block - 1) / per_block;
+    copy16<<<dim3((unsigned)grid), kBlock, 0, s>>>(reinterpret_cast<const u32x4 *>(src), reinterpret_cast<u32x4 *>(dst),
+                                                   n16);
     return hipGetLastError();
 }
 
