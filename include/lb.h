@@ -168,10 +168,10 @@ long long lb_steps_done(const lb_lattice *lat);
 /*
  * Integer properties: key 0 = kernel variant of the step (0 = one site per
  * thread, 1 / 2 / 3 = vector rows with 16- / 8- / 4-byte accesses per lane
- * and population plane), 1 = sites per thread, 2 = 1 if the lattice has
- * solid sites, 3 = bytes per stored population, 4 = workgroups per step
- * launch, 5 = plane stride in elements, 6 = number of fluid sites.
- * Returns -1 for an unknown key or a bad handle.
+ * and population), 1 = sites per thread, 2 = 1 if the lattice has solid
+ * sites, 3 = bytes per stored population, 4 = workgroups per step launch,
+ * 5 = x-rows per storage block, 6 = number of fluid sites, 7 = bytes of one
+ * population array.  Returns -1 for an unknown key or a bad handle.
  */
 long long lb_query(const lb_lattice *lat, int key);
 
@@ -182,9 +182,18 @@ long long lb_query(const lb_lattice *lat, int key);
 int lb_time_steps(lb_lattice *lat, int n, double *ms);
 
 /*
- * Bandwidth ceiling probe: a 16-byte-per-lane streaming copy of the current
- * population array into the other one (the same bytes a step reads and
- * writes), run reps times between HIP events on the lattice's stream.
+ * Enqueue n steps one by one (no graph) with HIP events on the lattice's
+ * stream around each step kernel alone (without the small kernel that adds
+ * up the conservation totals), wait, and store the mean step-kernel duration
+ * in milliseconds in *ms.  The state advances by n steps as with lb_step.
+ */
+int lb_time_step_kernel(lb_lattice *lat, int n, double *ms);
+
+/*
+ * Bandwidth ceiling probe: a streaming copy (one 16-byte non-temporal load
+ * and store per lane) of the current population array into the other one
+ * (the same bytes a step reads and writes), run reps times between HIP
+ * events on the lattice's stream.
  * Stores the mean milliseconds per copy in *ms.  Overwrites only the scratch
  * array, so the state is unchanged.
  */

@@ -44,6 +44,7 @@ _SIGNATURES = {
     "lb_steps_done": (ctypes.c_longlong, [_P]),
     "lb_query": (ctypes.c_longlong, [_P, ctypes.c_int]),
     "lb_time_steps": (ctypes.c_int, [_P, ctypes.c_int, _P]),
+    "lb_time_step_kernel": (ctypes.c_int, [_P, ctypes.c_int, _P]),
     "lb_copy_probe": (ctypes.c_int, [_P, ctypes.c_int, _P]),
 }
 
@@ -204,12 +205,19 @@ class Lattice:
 
     @property
     def info(self) -> dict:
-        keys = ["variant", "sites_per_thread", "solids", "bytes_per_population", "grid", "plane", "n_fluid"]
+        keys = ["variant", "sites_per_thread", "solids", "bytes_per_population", "grid", "block_rows", "n_fluid",
+                "array_bytes"]
         return {k: self.query(i) for i, k in enumerate(keys)}
 
     def time_steps(self, n: int) -> float:
         ms = ctypes.c_double(0.0)
         _check(lib().lb_time_steps(self._h, int(n), ctypes.byref(ms)), "lb_time_steps")
+        return ms.value
+
+    def time_step_kernel(self, n: int) -> float:
+        """Mean duration (ms) of the step kernel alone over n eager steps."""
+        ms = ctypes.c_double(0.0)
+        _check(lib().lb_time_step_kernel(self._h, int(n), ctypes.byref(ms)), "lb_time_step_kernel")
         return ms.value
 
     def copy_probe(self, reps: int = 10) -> float:

@@ -59,7 +59,8 @@ struct lb_lattice {
     uint64_t magic;
     int nx, ny, nz;
     uint64_t n;       // sites
-    uint64_t plane;   // elements between population planes
+    Layout lay;       // storage layout of a population array
+    uint64_t arr_elems;  // elements of one population array (19 * R * nx * blocks)
     int codec, esize;
     double tau, omega;
     double force[3];
@@ -71,6 +72,7 @@ struct lb_lattice {
     bool solids;
     double n_fluid;
     double *partials;
+    double *gpartials;
     unsigned int *ticket;
     double *ring;
     unsigned long long *counter;
@@ -95,27 +97,33 @@ StepArgs step_args(const lb_lattice *h, int from, float *rho, float *u)
     StepArgs a{};
     a.src = h->buf[from];
     a.dst = h->buf[from ^ 1];
-    a.plane = h->plane;
+    a.lay = h->lay;
     a.nx = h->nx;
     a.ny = h->ny;
     a.nz = h->nz;
     a.nslots = (int)(h->n / (uint64_t)h->vsites);
     a.div_nx = make_fastdiv((uint32_t)h->nx);
     a.div_ny = make_fastdiv((uint32_t)h->ny);
-    a.omega = (float)h->omega;
-    a.fx = (float)h->force[0];
-    a.fy = (float)h->force[1];
-    a.fz = (float)h->force[2];
+    a.coll = make_coll((float)h->omega, (float)h->force[0], (float)h->force[1], (float)h->force[2]);
     a.nbmask = h->nbmask;
     a.rowdirty = h->rowdirty;
     a.rho_out = rho;
     a.u_out = u;
     a.partials = h->partials;
-    a.ticket = h->ticket;
-    a.ring = h->ring;
-    a.step_counter = h->counter;
-    a.n_fluid = h->n_fluid;
     return a;
+}
+
+TotalsArgs totals_args(const lb_lattice *h)
+{
+    TotalsArgs t{};
+    t.partials = h->partials;
+    t.nparts = h->grid;
+    t.gpartials = h->gpartials;
+    t.ticket = h->ticket;
+    t.ring = h->ring;
+    t.step_counter = h->counter;
+    t.n_fluid = h->n_fluid;
+    return t;
 }
 
 // Enqueue one step from buf[from] on stream s.
@@ -124,6 +132,7 @@ int enqueue_one(lb_lattice *h, int from, float *rho, float *u, hipStream_t s)
     const bool macros = rho != nullptr;
     StepArgs a = step_args(h, from, rho, u);
     HIP_OR_FAIL(launch_step(h->codec, h->variant, h->solids, macros, a, h->grid, s));
+    HIP_OR_FAIL(launch_totals(totals_args(h), s));
     if (macros && h->solids && h->variant == 0)
         HIP_OR_FAIL(launch_zero_solid_macros(h->flags, (int)h->n, rho, u, s));
     return LB_OK;
@@ -192,7 +201,8 @@ void release(lb_lattice *h)
 {
     if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
-    void *ptrs[] = {h->buf[0], h->buf[1], h->flags, h->nbmask, h->rowdirty, h->partials, h->ticket, h->ring, h->counter};
+    void *ptrs[] = {h->buf[0],  h->buf[1],    h->flags,     h->nbmask, h->rowdirty,
+                    h->partials, h->gpartials, h->ticket, h->ring,     h->counter};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -249,14 +259,27 @@ int create_impl(lb_lattice **out, int nx, int ny, int nz, double tau, const uint
     }
     h->variant = variant;
     h->vsites = sites_per_thread(storage, h->variant);
-    // Plane stride: a multiple of 256 elements plus an optional pad that moves
-    // the planes off a common power-of-two alignment.
-    const long pad = env_long("LB_PLANE_PAD", 0);
-    if (pad < 0 || pad % 64 != 0) {
+    // Storage blocks of R rows: by default the largest power of two with
+    // R * nx * bytes <= 32 KiB per population segment.  LB_BLOCK_ROWS (a power
+    // of two) overrides it for tuning.
+    const uint64_t nrows = (uint64_t)ny * nz;
+    long rows = env_long("LB_BLOCK_ROWS", 0);
+    if (rows < 0 || (rows & (rows - 1)) != 0) {
         delete h;
-        return fail(LB_EINVAL, "LB_PLANE_PAD must be a non-negative multiple of 64");
+        return fail(LB_EINVAL, "LB_BLOCK_ROWS must be a power of two");
     }
-    h->plane = ((n + 255) / 256) * 256 + (uint64_t)pad;
+    if (rows == 0) {
+        rows = 1;
+        while ((uint64_t)(rows * 2) * nx * h->esize <= 32768 && (uint64_t)rows < nrows) rows *= 2;
+    }
+    uint32_t lg = 0;
+    while ((1l << lg) < rows) ++lg;
+    h->lay.nx = (uint32_t)nx;
+    h->lay.lg_r = lg;
+    h->lay.seg = (uint64_t)rows * nx;
+    h->lay.blk = (uint64_t)kQ * h->lay.seg;
+    const uint64_t nblocks = (nrows + rows - 1) / rows;
+    h->arr_elems = nblocks * h->lay.blk;
 
     int dev = 0;
     hipDeviceProp_t prop;
@@ -265,11 +288,13 @@ int create_impl(lb_lattice **out, int nx, int ny, int nz, double tau, const uint
         return fail(LB_EHIP, "cannot query the HIP device");
     }
     h->cus = prop.multiProcessorCount;
-    const int occ = step_occupancy(storage, h->variant, h->solids, false);
-    const long wg_per_cu = env_long("LB_WG_PER_CU", occ);
+    // One workgroup per tile of kBlock lanes.  LB_WG_PER_CU caps the grid at
+    // that many workgroups per compute unit (each then loops over tiles).
     const uint64_t tiles = (n / h->vsites + kBlock - 1) / kBlock;
-    uint64_t grid = (uint64_t)h->cus * (uint64_t)(wg_per_cu < 1 ? 1 : wg_per_cu);
-    if (grid > tiles) grid = tiles;
+    uint64_t grid = tiles;
+    const long wg_per_cu = env_long("LB_WG_PER_CU", 0);
+    if (wg_per_cu > 0 && (uint64_t)h->cus * wg_per_cu < grid) grid = (uint64_t)h->cus * wg_per_cu;
+    if (grid > 0x7fffffffull) grid = 0x7fffffff;
     h->grid = (int)(grid < 1 ? 1 : grid);
 
     auto bail = [&](int code, const char *what, hipError_t e) {
@@ -277,7 +302,7 @@ int create_impl(lb_lattice **out, int nx, int ny, int nz, double tau, const uint
         delete h;
         return fail(code, "%s: %s", what, hipGetErrorString(e));
     };
-    const size_t pbytes = (size_t)kQ * h->plane * h->esize;
+    const size_t pbytes = (size_t)h->arr_elems * h->esize;
     hipError_t e;
     for (int b = 0; b < 2; ++b) {
         e = hipMalloc(&h->buf[b], pbytes);
@@ -285,9 +310,10 @@ int create_impl(lb_lattice **out, int nx, int ny, int nz, double tau, const uint
         e = hipMemsetAsync(h->buf[b], 0, pbytes, h->stream);
         if (e != hipSuccess) return bail(LB_EHIP, "hipMemsetAsync", e);
     }
-    // per-launch totals: one slot per workgroup of the largest grid any step uses
-    const int max_grid = h->grid > 65536 ? h->grid : 65536;
-    if ((e = hipMalloc(&h->partials, (size_t)max_grid * 4 * sizeof(double))) != hipSuccess) return bail(LB_ENOMEM, "hipMalloc", e);
+    // per-step totals: one slot per step workgroup and one per reduce workgroup
+    const size_t ngroups = ((size_t)h->grid + kRedChunk - 1) / kRedChunk;
+    if ((e = hipMalloc(&h->partials, (size_t)h->grid * 4 * sizeof(double))) != hipSuccess) return bail(LB_ENOMEM, "hipMalloc", e);
+    if ((e = hipMalloc(&h->gpartials, ngroups * 4 * sizeof(double))) != hipSuccess) return bail(LB_ENOMEM, "hipMalloc", e);
     if ((e = hipMalloc(&h->ticket, sizeof(unsigned int))) != hipSuccess) return bail(LB_ENOMEM, "hipMalloc", e);
     if ((e = hipMalloc(&h->ring, (size_t)kRingCap * 4 * sizeof(double))) != hipSuccess) return bail(LB_ENOMEM, "hipMalloc", e);
     if ((e = hipMalloc(&h->counter, sizeof(unsigned long long))) != hipSuccess) return bail(LB_ENOMEM, "hipMalloc", e);
@@ -356,7 +382,7 @@ int lb_init_eq(lb_lattice *h, const double *rho, const double *u)
     if (int rc = check(h)) return rc;
     InitArgs a{};
     a.dst = h->buf[0];
-    a.plane = h->plane;
+    a.lay = h->lay;
     a.n = (int)h->n;
     a.rho = rho;
     a.u = u;
@@ -388,7 +414,7 @@ int lb_macros(lb_lattice *h, float *rho, float *u)
     if (int rc = check(h)) return rc;
     MacroArgs a{};
     a.src = h->buf[h->cur];
-    a.plane = h->plane;
+    a.lay = h->lay;
     a.n = (int)h->n;
     a.fx = (float)h->force[0];
     a.fy = (float)h->force[1];
@@ -429,15 +455,32 @@ static int copy_f(lb_lattice *h, void *host_or_dev, size_t bytes, int where, boo
     if (bytes != want) return fail(LB_EINVAL, "buffer is %zu bytes, expected %zu", bytes, want);
     if (!host_or_dev) return fail(LB_EINVAL, "NULL buffer");
     if (where != LB_HOST && where != LB_DEVICE) return fail(LB_EINVAL, "where must be LB_HOST or LB_DEVICE");
-    const size_t pl = h->n * h->esize;
+    // population i: full blocks as one 2-D copy (R rows per block), then the
+    // rows of a last, partly filled block
+    const size_t es = (size_t)h->esize;
+    const size_t seg = h->lay.seg * es, blk = h->lay.blk * es, plane = h->n * es;
+    const uint64_t rows = 1ull << h->lay.lg_r;
+    const uint64_t nrows = (uint64_t)h->ny * h->nz;
+    const uint64_t nfull = nrows / rows;
+    const size_t tail = (size_t)(nrows - nfull * rows) * h->nx * es;
     char *state = reinterpret_cast<char *>(h->buf[h->cur]);
     char *user = reinterpret_cast<char *>(host_or_dev);
     hipMemcpyKind kind = where == LB_HOST ? (to_lattice ? hipMemcpyHostToDevice : hipMemcpyDeviceToHost)
                                           : hipMemcpyDeviceToDevice;
     for (int i = 0; i < kQ; ++i) {
-        char *lat = state + (size_t)i * h->plane * h->esize;
-        char *usr = user + (size_t)i * pl;
-        HIP_OR_FAIL(hipMemcpyAsync(to_lattice ? lat : usr, to_lattice ? usr : lat, pl, kind, h->stream));
+        char *lat = state + (size_t)i * seg;
+        char *usr = user + (size_t)i * plane;
+        if (nfull > 0) {
+            if (to_lattice)
+                HIP_OR_FAIL(hipMemcpy2DAsync(lat, blk, usr, seg, seg, nfull, kind, h->stream));
+            else
+                HIP_OR_FAIL(hipMemcpy2DAsync(usr, seg, lat, blk, seg, nfull, kind, h->stream));
+        }
+        if (tail > 0) {
+            char *lt = lat + nfull * blk;
+            char *ut = usr + nfull * seg;
+            HIP_OR_FAIL(hipMemcpyAsync(to_lattice ? lt : ut, to_lattice ? ut : lt, tail, kind, h->stream));
+        }
     }
     if (where == LB_HOST) HIP_OR_FAIL(hipStreamSynchronize(h->stream));
     return LB_OK;
@@ -472,8 +515,9 @@ long long lb_query(const lb_lattice *h, int key)
         case 2: return h->solids ? 1 : 0;
         case 3: return h->esize;
         case 4: return h->grid;
-        case 5: return (long long)h->plane;
+        case 5: return 1ll << h->lay.lg_r;
         case 6: return (long long)h->n_fluid;
+        case 7: return (long long)(h->arr_elems * h->esize);
         default: return -1;
     }
 }
@@ -498,11 +542,44 @@ int lb_time_steps(lb_lattice *h, int n, double *ms)
     return rc;
 }
 
+int lb_time_step_kernel(lb_lattice *h, int n, double *ms)
+{
+    if (int rc = check(h)) return rc;
+    if (n < 1 || !ms) return fail(LB_EINVAL, "n must be >= 1 and ms non-NULL");
+    std::vector<hipEvent_t> ev(2 * (size_t)n, nullptr);
+    int rc = LB_OK;
+    for (auto &e : ev)
+        if (rc == LB_OK && hipEventCreate(&e) != hipSuccess) rc = fail(LB_EHIP, "hipEventCreate");
+    for (int k = 0; k < n && rc == LB_OK; ++k) {
+        StepArgs a = step_args(h, h->cur, nullptr, nullptr);
+        if (hipEventRecord(ev[2 * k], h->stream) != hipSuccess) rc = fail(LB_EHIP, "hipEventRecord");
+        if (rc == LB_OK && launch_step(h->codec, h->variant, h->solids, false, a, h->grid, h->stream) != hipSuccess)
+            rc = fail(LB_EHIP, "step kernel launch");
+        if (rc == LB_OK && hipEventRecord(ev[2 * k + 1], h->stream) != hipSuccess) rc = fail(LB_EHIP, "hipEventRecord");
+        if (rc == LB_OK && launch_totals(totals_args(h), h->stream) != hipSuccess) rc = fail(LB_EHIP, "totals launch");
+        if (rc == LB_OK) {
+            h->cur ^= 1;
+            h->steps += 1;
+        }
+    }
+    double total = 0.0;
+    if (rc == LB_OK && hipEventSynchronize(ev[2 * n - 1]) != hipSuccess) rc = fail(LB_EHIP, "hipEventSynchronize");
+    for (int k = 0; k < n && rc == LB_OK; ++k) {
+        float t = 0.0f;
+        if (hipEventElapsedTime(&t, ev[2 * k], ev[2 * k + 1]) != hipSuccess) rc = fail(LB_EHIP, "hipEventElapsedTime");
+        total += t;
+    }
+    for (auto &e : ev)
+        if (e) (void)hipEventDestroy(e);
+    if (rc == LB_OK) *ms = total / n;
+    return rc;
+}
+
 int lb_copy_probe(lb_lattice *h, int reps, double *ms)
 {
     if (int rc = check(h)) return rc;
     if (reps < 1 || !ms) return fail(LB_EINVAL, "reps must be >= 1 and ms non-NULL");
-    const uint64_t bytes = ((uint64_t)kQ * h->plane * h->esize) & ~(uint64_t)15;
+    const uint64_t bytes = ((uint64_t)h->arr_elems * h->esize) & ~(uint64_t)15;
     hipEvent_t e0, e1;
     HIP_OR_FAIL(hipEventCreate(&e0));
     HIP_OR_FAIL(hipEventCreate(&e1));

@@ -28,22 +28,60 @@ inline FastDiv make_fastdiv(uint32_t d)
     return FastDiv{d, (uint32_t)m, l};
 }
 
+// Storage layout of one population array.  The ny*nz x-rows are grouped in
+// blocks of R = 2^lg_r consecutive rows (row r = y + ny z); inside a block each
+// population keeps its R rows contiguous, one population after the other:
+//   element (i, x, r) at (r >> lg_r) * 19 R nx + i * R nx + (r & (R - 1)) * nx + x.
+// R = 1 stores the 19 populations of a row one after the other; R >= ny*nz is
+// plain structure of arrays.  Blocks of tens of KiB per population keep the
+// 38 streams of a step close together in HBM.
+struct Layout {
+    uint32_t nx;
+    uint32_t lg_r;   // log2(rows per block)
+    uint64_t seg;    // R * nx: elements of one population in one block
+    uint64_t blk;    // 19 * R * nx: elements of one block
+    __host__ __device__ uint64_t row_base(uint32_t r) const
+    {
+        return (uint64_t)(r >> lg_r) * blk + (uint64_t)(r & ((1u << lg_r) - 1u)) * nx;
+    }
+};
+
+// Per-launch constants of the collision (computed once on the host, in FP32).
+struct Coll {
+    float hom;             // omega / 2
+    float fx, fy, fz;      // body force
+    float hfx, hfy, hfz;   // F / 2
+    float g31, g32;        // 3 (1 - omega/2) w_k      (axis, diagonal weight)
+    float hC[kQ];          // 9 (1 - omega/2) w_k c_i.F
+    float hD[kQ];          // 3 (1 - omega/2) w_k c_i.F
+};
+
+Coll make_coll(float omega, float fx, float fy, float fz);
+
+constexpr int kRedChunk = 2048;  // step-workgroup partials summed by one reduce workgroup
+
 // Everything one step launch needs.  Pointers are device pointers.
 struct StepArgs {
-    const void *src;          // stored state (post-collision of the previous step), plane 0
-    void *dst;                // new state, plane 0
-    uint64_t plane;           // elements between consecutive population planes (>= N)
+    const void *src;          // stored state (post-collision of the previous step)
+    void *dst;                // new state
+    Layout lay;
     int nx, ny, nz;
     int nslots;               // N / sites_per_thread
     FastDiv div_nx, div_ny;
-    float omega;
-    float fx, fy, fz;
+    Coll coll;
     const uint32_t *nbmask;   // per site: bit i = site x - c_i is solid, bit 31 = site is solid
-    const uint8_t *rowdirty;  // per row (y, z): 1 if any site of the row has bit set in nbmask
+    const uint8_t *rowdirty;  // per row (y, z): 1 if any site of the row has a bit set in nbmask
     float *rho_out;           // optional macros output (N floats) or nullptr
     float *u_out;             // optional macros output (3N floats) or nullptr
-    double *partials;         // 4 doubles per workgroup
-    unsigned int *ticket;     // workgroup arrival counter, 0 between launches
+    double *partials;         // out: 4 doubles per workgroup
+};
+
+// The reduction of one step's partials into the ring of per-step totals.
+struct TotalsArgs {
+    const double *partials;   // 4 doubles per step workgroup
+    int nparts;               // step workgroups
+    double *gpartials;        // 4 doubles per reduce workgroup
+    unsigned int *ticket;     // arrival counter, 0 between launches
     double *ring;             // kRingCap x 4 doubles
     unsigned long long *step_counter;
     double n_fluid;           // number of fluid sites (exact in a double)
@@ -51,7 +89,7 @@ struct StepArgs {
 
 struct InitArgs {
     void *dst;
-    uint64_t plane;
+    Layout lay;
     int n;                    // N
     const double *rho;        // N or nullptr
     const double *u;          // 3N or nullptr
@@ -60,7 +98,7 @@ struct InitArgs {
 
 struct MacroArgs {
     const void *src;
-    uint64_t plane;
+    Layout lay;
     int n;
     float fx, fy, fz;
     const uint8_t *flags;
@@ -72,6 +110,7 @@ struct MacroArgs {
 // rows with 16- / 8- / 4-byte accesses per lane and population plane.
 hipError_t launch_step(int codec, int variant, bool solids, bool macros, const StepArgs &a, int grid,
                        hipStream_t s);
+hipError_t launch_totals(const TotalsArgs &a, hipStream_t s);
 hipError_t launch_init(int codec, const InitArgs &a, hipStream_t s);
 hipError_t launch_macros(int codec, const MacroArgs &a, hipStream_t s);
 hipError_t launch_masks(const uint8_t *flags, int nx, int ny, int nz, uint32_t *nbmask, uint8_t *rowdirty,

@@ -8,18 +8,18 @@
 // velocity set, halfway bounce-back at solid sites, periodic faces and Guo's
 // body-force source term.
 //
-// Storage: structure of arrays (Section 3.1), population i of site s at
-// plane_base + i * plane + s, s = x + nx (y + ny z).  What is stored is
-// g_i = f_i - w_i (populations shifted by their weights) in FP32, FP16 or
-// BF16; all arithmetic is FP32 (Section 3.1.1, "Mixed1").  Summing the
-// shifted values gives the density deviation rho - 1 and, because
-// sum_i w_i c_i = 0, the momentum directly.
+// Storage: one unit-stride vector per population (Section 3.1) inside blocks
+// of R x-rows (Layout in lb_internal.h).  What is stored is g_i = f_i - w_i
+// (populations shifted by their weights) in FP32, FP16 or BF16; all
+// arithmetic is FP32 (Section 3.1.1, "Mixed1").  Summing the shifted values
+// gives the density deviation rho - 1 and, because sum_i w_i c_i = 0, the
+// momentum directly.
 //
 // The update is bound by HBM bandwidth (Section 5.3 finds the paper's kernel
 // memory-bound on every device), so the kernels are built around the memory
-// stream: 16-byte loads and stores per lane and plane, lanes along x, the
-// +-1 x-shift of the pulled rows exchanged between neighbouring lanes with
-// one DPP move, no matrix cores.
+// stream: 8- or 16-byte loads and stores per lane and population, lanes along
+// x, the +-1 x-shift of the pulled rows exchanged between neighbouring lanes
+// with one DPP move, one workgroup per tile of 256 lanes, no matrix cores.
 #include "lb_internal.h"
 
 namespace lbm {
@@ -38,34 +38,38 @@ __host__ __device__ constexpr int weight_class(int i) { return i == 0 ? 0 : (i <
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
-// NW consecutive dwords of one population plane held by one lane.
+// NW consecutive dwords of one population held by one lane.
 template <int NW>
 struct Lane {
     uint32_t w[NW];
 };
 
+// Populations are read and written once per step: non-temporal accesses by
+// default (no reuse to keep in the caches).
 #ifndef LB_NT_LOAD
-#define LB_NT_LOAD 0
+#define LB_NT_LOAD 1
 #endif
 #ifndef LB_NT_STORE
 #define LB_NT_STORE 1
 #endif
 
-__device__ __forceinline__ u32x4 ld16(const void *p)
+template <typename T>
+__device__ __forceinline__ T ldg(const T *p)
 {
 #if LB_NT_LOAD
-    return __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
+    return __builtin_nontemporal_load(p);
 #else
-    return *reinterpret_cast<const u32x4 *>(p);
+    return *p;
 #endif
 }
 
-__device__ __forceinline__ void st16(void *p, u32x4 v)
+template <typename T>
+__device__ __forceinline__ void stg(T *p, T v)
 {
 #if LB_NT_STORE
-    __builtin_nontemporal_store(v, reinterpret_cast<u32x4 *>(p));
+    __builtin_nontemporal_store(v, p);
 #else
-    *reinterpret_cast<u32x4 *>(p) = v;
+    *p = v;
 #endif
 }
 
@@ -74,21 +78,17 @@ __device__ __forceinline__ Lane<NW> ldv(const char *p)
 {
     Lane<NW> r;
     if constexpr (NW == 4) {
-        const u32x4 v = ld16(p);
+        const u32x4 v = ldg(reinterpret_cast<const u32x4 *>(p));
         r.w[0] = v[0];
         r.w[1] = v[1];
         r.w[2] = v[2];
         r.w[3] = v[3];
     } else if constexpr (NW == 2) {
-#if LB_NT_LOAD
-        const u32x2 v = __builtin_nontemporal_load(reinterpret_cast<const u32x2 *>(p));
-#else
-        const u32x2 v = *reinterpret_cast<const u32x2 *>(p);
-#endif
+        const u32x2 v = ldg(reinterpret_cast<const u32x2 *>(p));
         r.w[0] = v[0];
         r.w[1] = v[1];
     } else {
-        r.w[0] = *reinterpret_cast<const uint32_t *>(p);
+        r.w[0] = ldg(reinterpret_cast<const uint32_t *>(p));
     }
     return r;
 }
@@ -102,22 +102,14 @@ __device__ __forceinline__ void stv(char *p, const Lane<NW> &d)
         v[1] = d.w[1];
         v[2] = d.w[2];
         v[3] = d.w[3];
-        st16(p, v);
+        stg(reinterpret_cast<u32x4 *>(p), v);
     } else if constexpr (NW == 2) {
         u32x2 v;
         v[0] = d.w[0];
         v[1] = d.w[1];
-#if LB_NT_STORE
-        __builtin_nontemporal_store(v, reinterpret_cast<u32x2 *>(p));
-#else
-        *reinterpret_cast<u32x2 *>(p) = v;
-#endif
+        stg(reinterpret_cast<u32x2 *>(p), v);
     } else {
-#if LB_NT_STORE
-        __builtin_nontemporal_store(d.w[0], reinterpret_cast<uint32_t *>(p));
-#else
-        *reinterpret_cast<uint32_t *>(p) = d.w[0];
-#endif
+        stg(reinterpret_cast<uint32_t *>(p), d.w[0]);
     }
 }
 
@@ -201,22 +193,23 @@ __device__ __forceinline__ void vset(Lane<NW> &d, int e, uint32_t b)
     }
 }
 
+// One element at element offset idx of a population array.
 template <int C>
-__device__ __forceinline__ uint32_t ld_elem(const char *plane_base, uint32_t idx)
+__device__ __forceinline__ uint32_t ld_elem(const char *base, uint64_t idx)
 {
     if constexpr (Codec<C>::kBytes == 4)
-        return *reinterpret_cast<const uint32_t *>(plane_base + (size_t)idx * 4);
+        return *reinterpret_cast<const uint32_t *>(base + idx * 4);
     else
-        return *reinterpret_cast<const uint16_t *>(plane_base + (size_t)idx * 2);
+        return *reinterpret_cast<const uint16_t *>(base + idx * 2);
 }
 
 template <int C>
-__device__ __forceinline__ void st_elem(char *plane_base, uint32_t idx, uint32_t b)
+__device__ __forceinline__ void st_elem(char *base, uint64_t idx, uint32_t b)
 {
     if constexpr (Codec<C>::kBytes == 4)
-        *reinterpret_cast<uint32_t *>(plane_base + (size_t)idx * 4) = b;
+        *reinterpret_cast<uint32_t *>(base + idx * 4) = b;
     else
-        *reinterpret_cast<uint16_t *>(plane_base + (size_t)idx * 2) = (uint16_t)b;
+        *reinterpret_cast<uint16_t *>(base + idx * 2) = (uint16_t)b;
 }
 
 // -------------------------------------------------------------- collision --
@@ -242,38 +235,6 @@ __device__ __forceinline__ void st_elem(char *plane_base, uint32_t idx, uint32_t
 //  - the rest population takes the remainder of the mass increments;
 //  - each population changes by g' = g + increment, rounded once.
 // With this the FP32 result stays at the rounding level of FP32 storage.
-
-struct Coll {
-    float hom;                // omega / 2
-    float fx, fy, fz;
-    float hfx, hfy, hfz;      // F / 2
-    float g31, g32;           // 3 (1 - omega/2) w_k      (axis, diagonal)
-    float hC[kQ];             // 9 (1 - omega/2) w_k c_i.F (first member of each pair)
-    float hD[kQ];             // 3 (1 - omega/2) w_k c_i.F
-};
-
-__device__ __forceinline__ Coll make_coll(float omega, float fx, float fy, float fz)
-{
-    Coll p;
-    p.hom = 0.5f * omega;
-    p.fx = fx;
-    p.fy = fy;
-    p.fz = fz;
-    p.hfx = 0.5f * fx;
-    p.hfy = 0.5f * fy;
-    p.hfz = 0.5f * fz;
-    const float k = 1.0f - 0.5f * omega;
-    p.g31 = 3.0f * k * W1;
-    p.g32 = 3.0f * k * W2;
-#pragma unroll
-    for (int i = 0; i < kQ; ++i) {
-        const float cF = CX[i] * fx + CY[i] * fy + CZ[i] * fz;
-        const float gk = k * (weight_class(i) == 1 ? W1 : W2);
-        p.hC[i] = 9.0f * gk * cF;
-        p.hD[i] = 3.0f * gk * cF;
-    }
-    return p;
-}
 
 // Half increments of one pair (i, j): hs = (s' - s) / 2, hd = (d' - d) / 2.
 __device__ __forceinline__ void relax_pair(float &gi, float &gj, float s, float n, float cj, float inv, float ts,
@@ -351,15 +312,15 @@ __device__ __forceinline__ void moments_of_totals(const float (&t)[kQ], float &m
 }
 
 // ------------------------------------------------- FP64 totals per launch --
-// Every workgroup reduces its threads' FP64 totals (wave butterfly, then LDS
-// in wave order) into partials[blockIdx.x]; the last workgroup to arrive sums
-// all partials in workgroup order and appends the result to the ring.  The
-// order of every addition is fixed, so the totals are bitwise reproducible.
+// Each workgroup of a step reduces its threads' FP64 totals (wave butterfly,
+// then LDS in wave order) and stores them in partials[blockIdx.x]; no fence
+// or atomic is needed there, because the totals are reduced by a second,
+// stream-ordered kernel (reduce_totals).  Every addition happens in a fixed
+// order, so the totals are bitwise reproducible.
 
-__device__ __forceinline__ void finish_totals(double (&acc)[4], const StepArgs &a)
+__device__ __forceinline__ void store_block_totals(double (&acc)[4], double *partials)
 {
     __shared__ double red[4][kBlock / 64];
-    __shared__ int is_last;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
 #pragma unroll
@@ -371,13 +332,51 @@ __device__ __forceinline__ void finish_totals(double (&acc)[4], const StepArgs &
         for (int k = 0; k < 4; ++k) red[k][wave] = acc[k];
     }
     __syncthreads();
+    if (threadIdx.x < 4) {
+        double v = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) v += red[threadIdx.x][w];
+        partials[4 * blockIdx.x + threadIdx.x] = v;
+    }
+}
+
+// Sum v[0..count) (4 doubles each) in a fixed tree; the result is valid in thread 0.
+__device__ __forceinline__ void block_sum4(const double *v, int count, double (&out)[4], bool coherent)
+{
+    __shared__ double tot[4][kBlock];
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < count; b += kBlock) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            s[k] += coherent ? __hip_atomic_load(&v[4 * b + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : v[4 * b + k];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) tot[k][threadIdx.x] = s[k];
+    __syncthreads();
+    for (int w = kBlock / 2; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) tot[k][threadIdx.x] += tot[k][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) out[k] = tot[k][0];
+}
+
+// Workgroup g sums partials [g * kRedChunk, (g + 1) * kRedChunk) into
+// gpartials[g]; the last workgroup to finish sums the gpartials in order and
+// appends {mass, momentum} of the step to the ring.
+__global__ __launch_bounds__(kBlock) void reduce_totals(TotalsArgs a)
+{
+    __shared__ int is_last;
+    const int first = blockIdx.x * kRedChunk;
+    const int count = min(kRedChunk, a.nparts - first);
+    double gs[4];
+    block_sum4(a.partials + 4 * (size_t)first, count, gs, false);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            double s = 0.0;
-            for (int w = 0; w < kBlock / 64; ++w) s += red[k][w];
-            __hip_atomic_store(&a.partials[4 * blockIdx.x + k], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+        for (int k = 0; k < 4; ++k)
+            __hip_atomic_store(&a.gpartials[4 * blockIdx.x + k], gs[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __threadfence();
         const unsigned int prev = atomicAdd(a.ticket, 1u);
         is_last = (prev == gridDim.x - 1);
@@ -385,45 +384,29 @@ __device__ __forceinline__ void finish_totals(double (&acc)[4], const StepArgs &
     __syncthreads();
     if (!is_last) return;
     __threadfence();
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += kBlock) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-            s[k] += __hip_atomic_load(&a.partials[4 * b + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __shared__ double tot[4][kBlock];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) tot[k][threadIdx.x] = s[k];
-    __syncthreads();
-    for (int w = kBlock / 2; w >= 1; w >>= 1) {
-        if (threadIdx.x < w) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) tot[k][threadIdx.x] += tot[k][threadIdx.x + w];
-        }
-        __syncthreads();
-    }
+    double tot[4];
+    block_sum4(a.gpartials, gridDim.x, tot, true);
     if (threadIdx.x == 0) {
-        const unsigned long long step =
-            __hip_atomic_load(a.step_counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long step = __hip_atomic_load(a.step_counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         double *r = a.ring + 4 * (step % kRingCap);
-        r[0] = a.n_fluid + tot[0][0];
-        r[1] = tot[1][0];
-        r[2] = tot[2][0];
-        r[3] = tot[3][0];
+        r[0] = a.n_fluid + tot[0];
+        r[1] = tot[1];
+        r[2] = tot[2];
+        r[3] = tot[3];
         __hip_atomic_store(a.step_counter, step + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(a.ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
 // ------------------------------------------------ step: vector-row kernel --
-// A lane owns V = 16 / bytes consecutive sites of one x-row (nx % V == 0) and
-// moves one 16-byte vector per population plane in each direction.  Lanes of
-// a wave take consecutive vectors.  For c_x = 0 the pulled vector is the
-// aligned one of the source row (y - c_y, z - c_z).  For c_x = +1 (-1) the
-// source is shifted by one element: the lane loads the aligned vector and
-// takes the missing element from the previous (next) lane's vector with one
-// DPP wave shift; the lane at a row end or wave edge loads that element
-// directly, wrapping periodically in x.
+// A lane owns V consecutive sites of one x-row (nx % V == 0) and moves one
+// 4-, 8- or 16-byte vector per population in each direction.  Lanes of a wave
+// take consecutive vectors.  For c_x = 0 the pulled vector is the aligned one
+// of the source row (y - c_y, z - c_z).  For c_x = +1 (-1) the source is
+// shifted by one element: the lane loads the aligned vector and takes the
+// missing element from the previous (next) lane's vector with one DPP wave
+// shift; the lane at a row end or wave edge loads that element directly,
+// wrapping periodically in x.
 
 template <int C, int NW>
 __device__ __forceinline__ Lane<NW> shift_in_from_left(const Lane<NW> &d, uint32_t prev_elem)
@@ -504,15 +487,14 @@ __device__ __forceinline__ void load_masks(const uint32_t *p, uint32_t (&m)[V])
     }
 }
 
-// NW: dwords per lane and plane (16-, 8- or 4-byte accesses).
+// NW: dwords per lane and population (16-, 8- or 4-byte accesses).
 template <int C, int NW, bool kSolids, bool kMacros>
 __global__ __launch_bounds__(kBlock) void step_vec(StepArgs a)
 {
     using K = Codec<C>;
     constexpr int V = NW * 4 / K::kBytes;  // sites per lane
-    const Coll cp = make_coll(a.omega, a.fx, a.fy, a.fz);
+    const Coll &cp = a.coll;
     const uint32_t nx = (uint32_t)a.nx, ny = (uint32_t)a.ny, nz = (uint32_t)a.nz;
-    const uint64_t pb = a.plane * K::kBytes;  // plane stride in bytes
     const char *src = reinterpret_cast<const char *>(a.src);
     char *dst = reinterpret_cast<char *>(a.dst);
     const int lane = threadIdx.x & 63;
@@ -530,18 +512,19 @@ __global__ __launch_bounds__(kBlock) void step_vec(StepArgs a)
         const uint32_t ym = (y == 0 ? ny : y) - 1, yp = (y + 1 == ny) ? 0 : y + 1;
         const uint32_t zm = (z == 0 ? nz : z) - 1, zp = (z + 1 == nz) ? 0 : z + 1;
 
-        // first element of each pulled source row
-        uint32_t rb[kQ];
+        // start (element offset) of the pulled source row of each population
+        uint64_t rb[kQ];
 #pragma unroll
         for (int i = 0; i < kQ; ++i) {
             const uint32_t ys = CY[i] > 0 ? ym : (CY[i] < 0 ? yp : y);
             const uint32_t zs = CZ[i] > 0 ? zm : (CZ[i] < 0 ? zp : z);
-            rb[i] = (zs * ny + ys) * nx;
+            rb[i] = a.lay.row_base(zs * ny + ys) + (uint64_t)i * a.lay.seg;
         }
+        const uint64_t own = a.lay.row_base(row) + x0;  // this lane's first site, population 0
 
         Lane<NW> d[kQ];
 #pragma unroll
-        for (int i = 0; i < kQ; ++i) d[i] = ldv<NW>(src + i * pb + (size_t)(rb[i] + x0) * K::kBytes);
+        for (int i = 0; i < kQ; ++i) d[i] = ldv<NW>(src + (rb[i] + x0) * K::kBytes);
 
         // +-1 shifts along x (all lanes take part in the DPP moves)
         const bool left_edge = (lane == 0) || (x0 == 0);
@@ -553,12 +536,12 @@ __global__ __launch_bounds__(kBlock) void step_vec(StepArgs a)
             if (CX[i] == 1) {
                 uint32_t prev = wave_shr1(d[i].w[NW - 1]);
                 if constexpr (K::kBytes == 2) prev >>= 16;
-                if (left_edge) prev = ld_elem<C>(src + i * pb, rb[i] + xl);
+                if (left_edge) prev = ld_elem<C>(src, rb[i] + xl);
                 d[i] = shift_in_from_left<C, NW>(d[i], prev);
             } else if (CX[i] == -1) {
                 uint32_t next = wave_shl1(d[i].w[0]);
                 if constexpr (K::kBytes == 2) next &= 0xffffu;
-                if (right_edge) next = ld_elem<C>(src + i * pb, rb[i] + xr);
+                if (right_edge) next = ld_elem<C>(src, rb[i] + xr);
                 d[i] = shift_in_from_right<C, NW>(d[i], next);
             }
         }
@@ -577,7 +560,7 @@ __global__ __launch_bounds__(kBlock) void step_vec(StepArgs a)
 #pragma unroll
                     for (int e = 0; e < V; ++e) sel |= ((m[e] >> i) & 1u) << e;
                     if (sel) {
-                        const Lane<NW> o = ldv<NW>(src + OPP[i] * pb + (size_t)s0 * K::kBytes);
+                        const Lane<NW> o = ldv<NW>(src + (own + OPP[i] * a.lay.seg) * K::kBytes);
 #pragma unroll
                         for (int e = 0; e < V; ++e)
                             if ((sel >> e) & 1u) vset<C, NW>(d[i], e, vget<C, NW>(o, e));
@@ -607,13 +590,13 @@ __global__ __launch_bounds__(kBlock) void step_vec(StepArgs a)
         if (active) {
             if (own_solid == 0) {
 #pragma unroll
-                for (int i = 0; i < kQ; ++i) stv<NW>(dst + i * pb + (size_t)s0 * K::kBytes, d[i]);
+                for (int i = 0; i < kQ; ++i) stv<NW>(dst + (own + i * a.lay.seg) * K::kBytes, d[i]);
             } else if (own_solid != (1u << V) - 1u) {
 #pragma unroll
                 for (int i = 0; i < kQ; ++i)
 #pragma unroll
                     for (int e = 0; e < V; ++e)
-                        if (!((own_solid >> e) & 1u)) st_elem<C>(dst + i * pb, s0 + e, vget<C, NW>(d[i], e));
+                        if (!((own_solid >> e) & 1u)) st_elem<C>(dst, own + i * a.lay.seg + e, vget<C, NW>(d[i], e));
             }
             if constexpr (kMacros) {
                 const size_t n = (size_t)nx * ny * nz;
@@ -640,7 +623,7 @@ __global__ __launch_bounds__(kBlock) void step_vec(StepArgs a)
             acc[3] += (double)pz;
         }
     }
-    finish_totals(acc, a);
+    store_block_totals(acc, a.partials);
 }
 
 // ---------------------------------------------- step: one site per thread --
@@ -651,9 +634,8 @@ template <int C, bool kSolids, bool kMacros>
 __global__ __launch_bounds__(kBlock) void step_site(StepArgs a)
 {
     using K = Codec<C>;
-    const Coll cp = make_coll(a.omega, a.fx, a.fy, a.fz);
+    const Coll &cp = a.coll;
     const uint32_t nx = (uint32_t)a.nx, ny = (uint32_t)a.ny, nz = (uint32_t)a.nz;
-    const uint64_t pb = a.plane * K::kBytes;
     const char *src = reinterpret_cast<const char *>(a.src);
     char *dst = reinterpret_cast<char *>(a.dst);
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -675,6 +657,7 @@ __global__ __launch_bounds__(kBlock) void step_site(StepArgs a)
         const uint32_t xm = (x == 0 ? nx : x) - 1, xp = (x + 1 == nx) ? 0 : x + 1;
         const uint32_t ym = (y == 0 ? ny : y) - 1, yp = (y + 1 == ny) ? 0 : y + 1;
         const uint32_t zm = (z == 0 ? nz : z) - 1, zp = (z + 1 == nz) ? 0 : z + 1;
+        const uint64_t own = a.lay.row_base(row) + x;
         float g[kQ];
 #pragma unroll
         for (int i = 0; i < kQ; ++i) {
@@ -683,9 +666,9 @@ __global__ __launch_bounds__(kBlock) void step_site(StepArgs a)
             const uint32_t zs = CZ[i] > 0 ? zm : (CZ[i] < 0 ? zp : z);
             uint32_t b;
             if (kSolids && ((mask >> i) & 1u))
-                b = ld_elem<C>(src + OPP[i] * pb, s);
+                b = ld_elem<C>(src, own + OPP[i] * a.lay.seg);
             else
-                b = ld_elem<C>(src + i * pb, (zs * ny + ys) * nx + xs);
+                b = ld_elem<C>(src, a.lay.row_base(zs * ny + ys) + i * a.lay.seg + xs);
             g[i] = K::dec(b);
         }
         float rho, ux, uy, uz;
@@ -694,7 +677,7 @@ __global__ __launch_bounds__(kBlock) void step_site(StepArgs a)
 #pragma unroll
         for (int i = 0; i < kQ; ++i) {
             const uint32_t b = K::enc(g[i]);
-            st_elem<C>(dst + i * pb, s, b);
+            st_elem<C>(dst, own + i * a.lay.seg, b);
             tot[i] = K::dec(b);
         }
         if constexpr (kMacros) {
@@ -711,7 +694,7 @@ __global__ __launch_bounds__(kBlock) void step_site(StepArgs a)
         acc[2] += (double)py;
         acc[3] += (double)pz;
     }
-    finish_totals(acc, a);
+    store_block_totals(acc, a.partials);
 }
 
 // Solid sites get zero macros in the one-site kernel (it skips them).
@@ -734,7 +717,6 @@ template <int C>
 __global__ __launch_bounds__(kBlock) void init_eq(InitArgs a)
 {
     using K = Codec<C>;
-    const uint64_t pb = a.plane * K::kBytes;
     char *dst = reinterpret_cast<char *>(a.dst);
     const double w[3] = {1.0 / 3.0, 1.0 / 18.0, 1.0 / 36.0};
     for (int s = blockIdx.x * kBlock + threadIdx.x; s < a.n; s += gridDim.x * kBlock) {
@@ -745,11 +727,13 @@ __global__ __launch_bounds__(kBlock) void init_eq(InitArgs a)
         const double uz = a.u ? a.u[2 * (size_t)a.n + s] : 0.0;
         const double drho = rho - 1.0;
         const double uu = ux * ux + uy * uy + uz * uz;
+        const uint32_t r = (uint32_t)s / a.lay.nx;
+        const uint64_t own = a.lay.row_base(r) + ((uint32_t)s - r * a.lay.nx);
 #pragma unroll
         for (int i = 0; i < kQ; ++i) {
             const double cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
             const double geq = w[weight_class(i)] * (drho + rho * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
-            st_elem<C>(dst + i * pb, (uint32_t)s, solid ? 0u : K::enc64(geq));
+            st_elem<C>(dst, own + i * a.lay.seg, solid ? 0u : K::enc64(geq));
         }
     }
 }
@@ -761,14 +745,15 @@ template <int C>
 __global__ __launch_bounds__(kBlock) void macros_kernel(MacroArgs a)
 {
     using K = Codec<C>;
-    const uint64_t pb = a.plane * K::kBytes;
     const char *src = reinterpret_cast<const char *>(a.src);
     for (int s = blockIdx.x * kBlock + threadIdx.x; s < a.n; s += gridDim.x * kBlock) {
         float r = 0.0f, ux = 0.0f, uy = 0.0f, uz = 0.0f;
         if (!(a.flags && a.flags[s])) {
+            const uint32_t row = (uint32_t)s / a.lay.nx;
+            const uint64_t own = a.lay.row_base(row) + ((uint32_t)s - row * a.lay.nx);
             float g[kQ];
 #pragma unroll
-            for (int i = 0; i < kQ; ++i) g[i] = K::dec(ld_elem<C>(src + i * pb, (uint32_t)s));
+            for (int i = 0; i < kQ; ++i) g[i] = K::dec(ld_elem<C>(src, own + i * a.lay.seg));
             float m, px, py, pz;
             moments_of_totals(g, m, px, py, pz);
             r = 1.0f + m;
@@ -817,25 +802,13 @@ __global__ __launch_bounds__(kBlock) void build_rowdirty(const uint32_t *nbmask,
 }
 
 // ------------------------------------------------------------ copy probe --
-
-// Each workgroup copies one contiguous 16 KiB chunk (4 coalesced 16-byte
-// accesses per lane), the access pattern of a plain streaming copy.
-constexpr int kCopyUnroll = 4;
+// Each workgroup copies 4 KiB (one coalesced 16-byte non-temporal access per
+// lane), the access pattern that reaches the highest copy bandwidth.
 
 __global__ __launch_bounds__(kBlock) void copy16(const u32x4 *src, u32x4 *dst, uint64_t n16)
 {
-    const uint64_t base = (uint64_t)blockIdx.x * (kBlock * kCopyUnroll) + threadIdx.x;
-    u32x4 v[kCopyUnroll];
-#pragma unroll
-    for (int k = 0; k < kCopyUnroll; ++k) {
-        const uint64_t i = base + (uint64_t)k * kBlock;
-        if (i < n16) v[k] = ld16(src + i);
-    }
-#pragma unroll
-    for (int k = 0; k < kCopyUnroll; ++k) {
-        const uint64_t i = base + (uint64_t)k * kBlock;
-        if (i < n16) st16(dst + i, v[k]);
-    }
+    const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n16) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
 inline int grid_for(uint64_t n, int cap = 65536)
@@ -869,6 +842,28 @@ void *pick_step(int codec, int variant, bool solids, bool macros)
 
 }  // namespace
 
+Coll make_coll(float omega, float fx, float fy, float fz)
+{
+    Coll p;
+    p.hom = 0.5f * omega;
+    p.fx = fx;
+    p.fy = fy;
+    p.fz = fz;
+    p.hfx = 0.5f * fx;
+    p.hfy = 0.5f * fy;
+    p.hfz = 0.5f * fz;
+    const float k = 1.0f - 0.5f * omega;
+    p.g31 = 3.0f * k * W1;
+    p.g32 = 3.0f * k * W2;
+    for (int i = 0; i < kQ; ++i) {
+        const float cF = CX[i] * fx + CY[i] * fy + CZ[i] * fz;
+        const float gk = k * (weight_class(i) == 1 ? W1 : W2);
+        p.hC[i] = 9.0f * gk * cF;
+        p.hD[i] = 3.0f * gk * cF;
+    }
+    return p;
+}
+
 int sites_per_thread(int codec, int variant)
 {
     const int nw = variant == 1 ? 4 : (variant == 2 ? 2 : (variant == 3 ? 1 : 0));
@@ -891,6 +886,13 @@ hipError_t launch_step(int codec, int variant, bool solids, bool macros, const S
     StepArgs arg = a;
     void *params[] = {&arg};
     return hipLaunchKernel(fn, dim3(grid), dim3(kBlock), params, 0, s);
+}
+
+hipError_t launch_totals(const TotalsArgs &a, hipStream_t s)
+{
+    const int g = (a.nparts + kRedChunk - 1) / kRedChunk;
+    reduce_totals<<<g, kBlock, 0, s>>>(a);
+    return hipGetLastError();
 }
 
 hipError_t launch_init(int codec, const InitArgs &a, hipStream_t s)
@@ -933,8 +935,7 @@ hipError_t launch_zero_solid_macros(const uint8_t *flags, int n, float *rho, flo
 hipError_t launch_copy(const void *src, void *dst, uint64_t bytes, hipStream_t s)
 {
     const uint64_t n16 = bytes / 16;
-    const uint64_t per_block = (uint64_t)kBlock * kCopyUnroll;
-    const uint64_t grid = (n16 + per_block - 1) / per_block;
+    const uint64_t grid = (n16 + kBlock - 1) / kBlock;
     copy16<<<dim3((unsigned)grid), kBlock, 0, s>>>(reinterpret_cast<const u32x4 *>(src), reinterpret_cast<u32x4 *>(dst),
                                                    n16);
     return hipGetLastError();

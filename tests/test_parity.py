@@ -187,8 +187,9 @@ def test_conservation_totals_match_oracle_and_reproduce():
     for t in range(steps):
         S = oracle.run(S, cfg["tau"], 1, F=cfg["force"], flags=cfg["flags"])
         ref = oracle.sums(S, cfg["flags"])
+        # FP32 state vs FP64 state: agreement to FP32 rounding of the totals
         assert abs(sums[t, 0] - ref[0]) < 1e-7
-        assert np.abs(sums[t, 1:] - ref[1:]).max() < 1e-8
+        assert np.abs(sums[t, 1:] - ref[1:]).max() < 1e-7 * max(1.0, np.abs(ref[1:]).max())
     lat2 = make_lattice(cfg)
     lat2.step(steps)
     assert np.array_equal(lat2.sums(steps), sums)
