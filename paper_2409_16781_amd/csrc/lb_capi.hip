@@ -241,10 +241,12 @@ int create_impl(lb_lattice **out, int nx, int ny, int nz, double tau, const uint
     h->solids = nsolid > 0;
     h->n_fluid = (double)(n - nsolid);
 
-    // Step kernel: vector rows when nx is a multiple of the sites per lane,
-    // else one site per thread.  LB_KERNEL (0..3) overrides for tuning.
+    // Step kernel: vector rows with 16-byte (FP32) or 8-byte (16-bit codecs)
+    // accesses, 4 sites per lane; narrower vectors when nx is not a multiple
+    // of 4, one site per thread when no vector width divides nx.
+    // LB_KERNEL (0..3) overrides the choice for tuning.
     const long kernel = env_long("LB_KERNEL", -1);
-    int variant = 2;
+    int variant = storage == LB_F32 ? 1 : 2;
     if (kernel >= 0 && kernel <= 3) variant = (int)kernel;
     else if (kernel != -1) {
         delete h;
@@ -255,7 +257,9 @@ int create_impl(lb_lattice **out, int nx, int ny, int nz, double tau, const uint
             delete h;
             return fail(LB_EINVAL, "kernel %d needs nx %% %d == 0", variant, sites_per_thread(storage, variant));
         }
-        variant = (variant <= 2 && nx % sites_per_thread(storage, 3) == 0) ? 3 : 0;
+        int v = variant + 1;
+        while (v <= 3 && nx % sites_per_thread(storage, v) != 0) ++v;
+        variant = v <= 3 ? v : 0;
     }
     h->variant = variant;
     h->vsites = sites_per_thread(storage, h->variant);

@@ -52,6 +52,8 @@ struct Coll {
     float fx, fy, fz;      // body force
     float hfx, hfy, hfz;   // F / 2
     float g31, g32;        // 3 (1 - omega/2) w_k      (axis, diagonal weight)
+    float ow1, ow2;        // omega w_k
+    float q1, q2;          // (9/2) omega w_k
     float hC[kQ];          // 9 (1 - omega/2) w_k c_i.F
     float hD[kQ];          // 3 (1 - omega/2) w_k c_i.F
 };

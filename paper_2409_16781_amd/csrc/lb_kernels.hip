@@ -134,25 +134,41 @@ struct Codec<kF32> {
     __device__ static uint32_t enc64(double v) { return __builtin_bit_cast(uint32_t, (float)v); }
 };
 
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// 16-bit codecs also work on the two elements of one dword at once: packed
+// conversion (one instruction, round to nearest even) and a dot product with
+// (1, 1) for the sum of the pair in FP32.
 template <>
 struct Codec<kF16> {
     static constexpr int kBytes = 2;
     __device__ static float dec(uint32_t b) { return (float)__builtin_bit_cast(_Float16, (uint16_t)b); }
     __device__ static uint32_t enc(float v) { return __builtin_bit_cast(uint16_t, (_Float16)v); }
     __device__ static uint32_t enc64(double v) { return __builtin_bit_cast(uint16_t, (_Float16)v); }
+    __device__ static void dec2(uint32_t w, float &lo, float &hi)
+    {
+        lo = dec(w & 0xffffu);
+        hi = dec(w >> 16);
+    }
+    __device__ static uint32_t enc2(float lo, float hi)
+    {
+        f32x2 v = {lo, hi};
+        return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, f16x2));
+    }
+    __device__ static float sum2(uint32_t w, float acc)
+    {
+        const f16x2 one = {(_Float16)1.0f, (_Float16)1.0f};
+        return __builtin_amdgcn_fdot2(__builtin_bit_cast(f16x2, w), one, acc, false);
+    }
 };
 
 template <>
 struct Codec<kBF16> {
     static constexpr int kBytes = 2;
     __device__ static float dec(uint32_t b) { return __builtin_bit_cast(float, b << 16); }
-    __device__ static uint32_t enc(float v)
-    {
-        uint32_t u = __builtin_bit_cast(uint32_t, v);
-        if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0u;  // NaN stays a quiet NaN
-        u += 0x7fffu + ((u >> 16) & 1u);
-        return u >> 16;
-    }
+    __device__ static uint32_t enc(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
     // Nearest bfloat16 to a double (one rounding): pick among the neighbours of
     // the float-rounded candidate.
     __device__ static uint32_t enc64(double v)
@@ -169,6 +185,21 @@ struct Codec<kBF16> {
             }
         }
         return best;
+    }
+    __device__ static void dec2(uint32_t w, float &lo, float &hi)
+    {
+        lo = __builtin_bit_cast(float, w << 16);
+        hi = __builtin_bit_cast(float, w & 0xffff0000u);
+    }
+    __device__ static uint32_t enc2(float lo, float hi)
+    {
+        f32x2 v = {lo, hi};
+        return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+    }
+    __device__ static float sum2(uint32_t w, float acc)
+    {
+        const bf16x2 one = {(__bf16)1.0f, (__bf16)1.0f};
+        return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, w), one, acc, false);
     }
 };
 
@@ -236,13 +267,15 @@ __device__ __forceinline__ void st_elem(char *base, uint64_t idx, uint32_t b)
 //  - each population changes by g' = g + increment, rounded once.
 // With this the FP32 result stays at the rounding level of FP32 storage.
 
-// Half increments of one pair (i, j): hs = (s' - s) / 2, hd = (d' - d) / 2.
-__device__ __forceinline__ void relax_pair(float &gi, float &gj, float s, float n, float cj, float inv, float ts,
-                                           float nw, float e, float hC, float hD, float hom, float &sum_hs)
+// Half increments of one pair (i, j): hs = (s' - s) / 2, hd = (d' - d) / 2,
+//   hs = (omega/2) (s^eq - s) + (S_i + S_opp)/2
+//      = cu (q c.j + hC) + base - (omega/2) s,   q = (9/2) omega w_k,
+//   base = omega w_k (drho - 3/2 j.u) - 3 (1 - omega/2) w_k u.F.
+__device__ __forceinline__ void relax_pair(float &gi, float &gj, float s, float n, float cj, float inv, float base,
+                                           float q, float hC, float hD, float hom, float &sum_hs)
 {
     const float cu = cj * inv;
-    const float seq = (nw * cj) * cu + ts;
-    const float hs = hom * (seq - s) + (hC * cu - e);
+    const float hs = cu * (q * cj + hC) + base - hom * s;
     const float hd = hD - hom * n;
     gi = gi + (hs + hd);
     gj = gj + (hs - hd);
@@ -267,15 +300,16 @@ __device__ __forceinline__ void collide(float (&g)[kQ], const Coll &p, float &rh
     const float jy = (d3 + d7 - d8 + d15 + d16) + p.hfy;
     const float jz = (d5 + d11 - d12 + d15 - d16) + p.hfz;
     rho = 1.0f + drho;
-    const float inv = 1.0f / rho;
+    // 1/rho enters only the second-order terms and the reported velocity; the
+    // hardware reciprocal (1 ulp) is accurate enough for both
+    const float inv = __builtin_amdgcn_rcpf(rho);
     ux = jx * inv;
     uy = jy * inv;
     uz = jz * inv;
     const float ju = jx * ux + jy * uy + jz * uz;  // rho u.u
     const float uF = ux * p.fx + uy * p.fy + uz * p.fz;
     const float t = drho - 1.5f * ju;
-    const float ts1 = (2.0f * W1) * t, ts2 = (2.0f * W2) * t;
-    const float e1 = p.g31 * uF, e2 = p.g32 * uF;
+    const float base1 = p.ow1 * t - p.g31 * uF, base2 = p.ow2 * t - p.g32 * uF;
 
     // odd non-equilibrium parts: diagonals directly, axes as the remainder
     const float c7 = jx + jy, c8 = jx - jy, c11 = jx + jz, c12 = jx - jz, c15 = jy + jz, c16 = jy - jz;
@@ -287,17 +321,16 @@ __device__ __forceinline__ void collide(float (&g)[kQ], const Coll &p, float &rh
     const float n3 = -p.hfy - ((n7 - n8) + (n15 + n16));
     const float n5 = -p.hfz - ((n11 - n12) + (n15 - n16));
 
-    constexpr float kNW1 = 9.0f * W1, kNW2 = 9.0f * W2;
     float sum_hs = 0.0f;
-    relax_pair(g[1], g[2], s1, n1, jx, inv, ts1, kNW1, e1, p.hC[1], p.hD[1], p.hom, sum_hs);
-    relax_pair(g[3], g[4], s3, n3, jy, inv, ts1, kNW1, e1, p.hC[3], p.hD[3], p.hom, sum_hs);
-    relax_pair(g[5], g[6], s5, n5, jz, inv, ts1, kNW1, e1, p.hC[5], p.hD[5], p.hom, sum_hs);
-    relax_pair(g[7], g[10], s7, n7, c7, inv, ts2, kNW2, e2, p.hC[7], p.hD[7], p.hom, sum_hs);
-    relax_pair(g[8], g[9], s8, n8, c8, inv, ts2, kNW2, e2, p.hC[8], p.hD[8], p.hom, sum_hs);
-    relax_pair(g[11], g[14], s11, n11, c11, inv, ts2, kNW2, e2, p.hC[11], p.hD[11], p.hom, sum_hs);
-    relax_pair(g[12], g[13], s12, n12, c12, inv, ts2, kNW2, e2, p.hC[12], p.hD[12], p.hom, sum_hs);
-    relax_pair(g[15], g[18], s15, n15, c15, inv, ts2, kNW2, e2, p.hC[15], p.hD[15], p.hom, sum_hs);
-    relax_pair(g[16], g[17], s16, n16, c16, inv, ts2, kNW2, e2, p.hC[16], p.hD[16], p.hom, sum_hs);
+    relax_pair(g[1], g[2], s1, n1, jx, inv, base1, p.q1, p.hC[1], p.hD[1], p.hom, sum_hs);
+    relax_pair(g[3], g[4], s3, n3, jy, inv, base1, p.q1, p.hC[3], p.hD[3], p.hom, sum_hs);
+    relax_pair(g[5], g[6], s5, n5, jz, inv, base1, p.q1, p.hC[5], p.hD[5], p.hom, sum_hs);
+    relax_pair(g[7], g[10], s7, n7, c7, inv, base2, p.q2, p.hC[7], p.hD[7], p.hom, sum_hs);
+    relax_pair(g[8], g[9], s8, n8, c8, inv, base2, p.q2, p.hC[8], p.hD[8], p.hom, sum_hs);
+    relax_pair(g[11], g[14], s11, n11, c11, inv, base2, p.q2, p.hC[11], p.hD[11], p.hom, sum_hs);
+    relax_pair(g[12], g[13], s12, n12, c12, inv, base2, p.q2, p.hC[12], p.hD[12], p.hom, sum_hs);
+    relax_pair(g[15], g[18], s15, n15, c15, inv, base2, p.q2, p.hC[15], p.hD[15], p.hom, sum_hs);
+    relax_pair(g[16], g[17], s16, n16, c16, inv, base2, p.q2, p.hC[16], p.hD[16], p.hom, sum_hs);
     g[0] = g[0] - 2.0f * sum_hs;
 }
 
@@ -312,30 +345,30 @@ __device__ __forceinline__ void moments_of_totals(const float (&t)[kQ], float &m
 }
 
 // ------------------------------------------------- FP64 totals per launch --
-// Each workgroup of a step reduces its threads' FP64 totals (wave butterfly,
-// then LDS in wave order) and stores them in partials[blockIdx.x]; no fence
+// Each workgroup of a step reduces its threads' FP64 totals (through LDS in a
+// fixed tree) and stores them in partials[blockIdx.x]; no fence
 // or atomic is needed there, because the totals are reduced by a second,
 // stream-ordered kernel (reduce_totals).  Every addition happens in a fixed
 // order, so the totals are bitwise reproducible.
 
-__device__ __forceinline__ void store_block_totals(double (&acc)[4], double *partials)
+__device__ __forceinline__ void store_block_totals(const double (&acc)[4], double *partials)
 {
-    __shared__ double red[4][kBlock / 64];
+    __shared__ double red[4][kBlock];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) acc[k] += __shfl_xor(acc[k], off, 64);
-    }
-    const int wave = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) red[k][wave] = acc[k];
-    }
+    for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = acc[k];
     __syncthreads();
-    if (threadIdx.x < 4) {
-        double v = 0.0;
-        for (int w = 0; w < kBlock / 64; ++w) v += red[threadIdx.x][w];
-        partials[4 * blockIdx.x + threadIdx.x] = v;
+    if (threadIdx.x < 64) {
+        double v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            v[k] = (red[k][threadIdx.x] + red[k][threadIdx.x + 64]) + (red[k][threadIdx.x + 128] + red[k][threadIdx.x + 192]);
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+        }
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) partials[4 * blockIdx.x + k] = v[k];
+        }
     }
 }
 
@@ -487,9 +520,15 @@ __device__ __forceinline__ void load_masks(const uint32_t *p, uint32_t (&m)[V])
     }
 }
 
+// Register budget of the vector-row kernels, as waves per SIMD the compiler
+// must fit (the unrolled site loop otherwise favours latency over occupancy).
+#ifndef LB_VEC_WAVES
+#define LB_VEC_WAVES 1
+#endif
+
 // NW: dwords per lane and population (16-, 8- or 4-byte accesses).
 template <int C, int NW, bool kSolids, bool kMacros>
-__global__ __launch_bounds__(kBlock) void step_vec(StepArgs a)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(LB_VEC_WAVES))) void step_vec(StepArgs a)
 {
     using K = Codec<C>;
     constexpr int V = NW * 4 / K::kBytes;  // sites per lane
@@ -569,22 +608,35 @@ __global__ __launch_bounds__(kBlock) void step_vec(StepArgs a)
             }
         }
 
-        // collide site by site
+        // collide site by site (16-bit codecs: two sites per dword at a time)
         float mr[V], mu[V], mv[V], mw[V];
+        if constexpr (K::kBytes == 4) {
 #pragma unroll
-        for (int e = 0; e < V; ++e) {
-            float g[kQ];
+            for (int e = 0; e < V; ++e) {
+                float g[kQ];
 #pragma unroll
-            for (int i = 0; i < kQ; ++i) g[i] = K::dec(vget<C, NW>(d[i], e));
-            float rho, ux, uy, uz;
-            collide(g, cp, rho, ux, uy, uz);
+                for (int i = 0; i < kQ; ++i) g[i] = K::dec(d[i].w[e]);
+                collide(g, cp, mr[e], mu[e], mv[e], mw[e]);
 #pragma unroll
-            for (int i = 0; i < kQ; ++i) vset<C, NW>(d[i], e, K::enc(g[i]));
-            const bool fluid = !((own_solid >> e) & 1u);
-            mr[e] = fluid ? rho : 0.0f;
-            mu[e] = fluid ? ux : 0.0f;
-            mv[e] = fluid ? uy : 0.0f;
-            mw[e] = fluid ? uz : 0.0f;
+                for (int i = 0; i < kQ; ++i) d[i].w[e] = K::enc(g[i]);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < NW; ++j) {
+                float g0[kQ], g1[kQ];
+#pragma unroll
+                for (int i = 0; i < kQ; ++i) K::dec2(d[i].w[j], g0[i], g1[i]);
+                collide(g0, cp, mr[2 * j], mu[2 * j], mv[2 * j], mw[2 * j]);
+                collide(g1, cp, mr[2 * j + 1], mu[2 * j + 1], mv[2 * j + 1], mw[2 * j + 1]);
+#pragma unroll
+                for (int i = 0; i < kQ; ++i) d[i].w[j] = K::enc2(g0[i], g1[i]);
+            }
+        }
+        if constexpr (kSolids || kMacros) {
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                if ((own_solid >> e) & 1u) mr[e] = mu[e] = mv[e] = mw[e] = 0.0f;
+            }
         }
 
         if (active) {
@@ -607,13 +659,28 @@ __global__ __launch_bounds__(kBlock) void step_vec(StepArgs a)
             }
             // totals of the values as stored (after rounding), fluid sites only
             float tot[kQ];
+            if (own_solid == 0) {
 #pragma unroll
-            for (int i = 0; i < kQ; ++i) {
-                float t = 0.0f;
+                for (int i = 0; i < kQ; ++i) {
+                    float t = 0.0f;
 #pragma unroll
-                for (int e = 0; e < V; ++e)
-                    if (!((own_solid >> e) & 1u)) t += K::dec(vget<C, NW>(d[i], e));
-                tot[i] = t;
+                    for (int j = 0; j < NW; ++j) {
+                        if constexpr (K::kBytes == 4)
+                            t += K::dec(d[i].w[j]);
+                        else
+                            t = K::sum2(d[i].w[j], t);
+                    }
+                    tot[i] = t;
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < kQ; ++i) {
+                    float t = 0.0f;
+#pragma unroll
+                    for (int e = 0; e < V; ++e)
+                        if (!((own_solid >> e) & 1u)) t += K::dec(vget<C, NW>(d[i], e));
+                    tot[i] = t;
+                }
             }
             float m, px, py, pz;
             moments_of_totals(tot, m, px, py, pz);
@@ -855,6 +922,10 @@ Coll make_coll(float omega, float fx, float fy, float fz)
     const float k = 1.0f - 0.5f * omega;
     p.g31 = 3.0f * k * W1;
     p.g32 = 3.0f * k * W2;
+    p.ow1 = omega * W1;
+    p.ow2 = omega * W2;
+    p.q1 = 4.5f * omega * W1;
+    p.q2 = 4.5f * omega * W2;
     for (int i = 0; i < kQ; ++i) {
         const float cF = CX[i] * fx + CY[i] * fy + CZ[i] * fz;
         const float gk = k * (weight_class(i) == 1 ? W1 : W2);
