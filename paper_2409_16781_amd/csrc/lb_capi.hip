@@ -102,6 +102,14 @@ StepArgs step_args(const lb_lattice *h, int from, float *rho, float *u)
     a.ny = h->ny;
     a.nz = h->nz;
     a.nslots = (int)(h->n / (uint64_t)h->vsites);
+    // tiles of kBlock lanes hold whole rows when the lanes per row divide kBlock
+    const int row_lanes = h->nx / h->vsites;
+    a.lds_edges = (h->variant != 0 && h->nx % h->vsites == 0 && row_lanes <= kBlock && (kBlock % row_lanes) == 0 &&
+                   env_long("LB_LDS_EDGES", 1) != 0)
+                      ? 1
+                      : 0;
+    a.lg_row_lanes = 0;
+    while ((1 << a.lg_row_lanes) < row_lanes) ++a.lg_row_lanes;
     a.div_nx = make_fastdiv((uint32_t)h->nx);
     a.div_ny = make_fastdiv((uint32_t)h->ny);
     a.coll = make_coll((float)h->omega, (float)h->force[0], (float)h->force[1], (float)h->force[2]);

@@ -69,6 +69,8 @@ struct StepArgs {
     Layout lay;
     int nx, ny, nz;
     int nslots;               // N / sites_per_thread
+    int lds_edges;            // 1: every tile holds whole x-rows (x-edge elements via LDS)
+    int lg_row_lanes;         // log2(lanes per x-row) when lds_edges
     FastDiv div_nx, div_ny;
     Coll coll;
     const uint32_t *nbmask;   // per site: bit i = site x - c_i is solid, bit 31 = site is solid

@@ -473,6 +473,10 @@ __device__ __forceinline__ Lane<NW> shift_in_from_right(const Lane<NW> &d, uint3
     return r;
 }
 
+// Directions with c_x = +1 and c_x = -1.
+constexpr int kPlusX[5] = {1, 7, 8, 11, 12};
+constexpr int kMinusX[5] = {2, 9, 10, 13, 14};
+
 // DPP wave shifts: lane l receives lane l-1 (shr) or lane l+1 (shl).
 __device__ __forceinline__ uint32_t wave_shr1(uint32_t v)
 {
@@ -521,14 +525,22 @@ __device__ __forceinline__ void load_masks(const uint32_t *p, uint32_t (&m)[V])
 }
 
 // Register budget of the vector-row kernels, as waves per SIMD the compiler
-// must fit (the unrolled site loop otherwise favours latency over occupancy).
-#ifndef LB_VEC_WAVES
-#define LB_VEC_WAVES 1
+// must fit (the unrolled site loop otherwise favours latency over occupancy):
+// three for the 16-bit codecs with 4- or 8-byte vectors (fits without
+// spills), no constraint otherwise.
+template <int C, int NW>
+constexpr int vec_waves()
+{
+#ifdef LB_VEC_WAVES
+    return LB_VEC_WAVES;
+#else
+    return (Codec<C>::kBytes == 2 && NW <= 2) ? 3 : 1;
 #endif
+}
 
 // NW: dwords per lane and population (16-, 8- or 4-byte accesses).
 template <int C, int NW, bool kSolids, bool kMacros>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(LB_VEC_WAVES))) void step_vec(StepArgs a)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(vec_waves<C, NW>()))) void step_vec(StepArgs a)
 {
     using K = Codec<C>;
     constexpr int V = NW * 4 / K::kBytes;  // sites per lane
@@ -539,6 +551,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(LB_VEC_W
     const int lane = threadIdx.x & 63;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     const int ntiles = (a.nslots + kBlock - 1) / kBlock;
+    // x-edge elements exchanged between lanes of a tile: the last (first)
+    // dword of each row and wave, for the five c_x = +1 (-1) directions
+    __shared__ uint32_t edge_row_last[kBlock][5], edge_row_first[kBlock][5];
+    __shared__ uint32_t edge_wave_last[kBlock / 64][5], edge_wave_first[kBlock / 64][5];
 
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int slot = tile * kBlock + (int)threadIdx.x;
@@ -565,24 +581,63 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(LB_VEC_W
 #pragma unroll
         for (int i = 0; i < kQ; ++i) d[i] = ldv<NW>(src + (rb[i] + x0) * K::kBytes);
 
-        // +-1 shifts along x (all lanes take part in the DPP moves)
+        // +-1 shifts along x (all lanes take part in the DPP moves).  The
+        // element a lane needs from beyond its wave or across the periodic
+        // wrap comes through LDS when the tile holds whole rows (each
+        // element is then read from HBM once), else by a direct load.
         const bool left_edge = (lane == 0) || (x0 == 0);
         const bool right_edge = (lane == 63) || (x0 + V == nx);
+        const int wave = threadIdx.x >> 6;
+        const int rit = (int)threadIdx.x >> a.lg_row_lanes;  // row within the tile
+        if (a.lds_edges) {
+            __syncthreads();  // the previous tile's readers are done
+            if (x0 + V == nx) {
+#pragma unroll
+                for (int k = 0; k < 5; ++k) edge_row_last[rit][k] = d[kPlusX[k]].w[NW - 1];
+            }
+            if (x0 == 0) {
+#pragma unroll
+                for (int k = 0; k < 5; ++k) edge_row_first[rit][k] = d[kMinusX[k]].w[0];
+            }
+            if (lane == 63) {
+#pragma unroll
+                for (int k = 0; k < 5; ++k) edge_wave_last[wave][k] = d[kPlusX[k]].w[NW - 1];
+            }
+            if (lane == 0) {
+#pragma unroll
+                for (int k = 0; k < 5; ++k) edge_wave_first[wave][k] = d[kMinusX[k]].w[0];
+            }
+            __syncthreads();
+        }
         const uint32_t xl = (x0 == 0 ? nx : x0) - 1;
         const uint32_t xr = (x0 + V == nx) ? 0 : x0 + V;
 #pragma unroll
-        for (int i = 0; i < kQ; ++i) {
-            if (CX[i] == 1) {
-                uint32_t prev = wave_shr1(d[i].w[NW - 1]);
-                if constexpr (K::kBytes == 2) prev >>= 16;
-                if (left_edge) prev = ld_elem<C>(src, rb[i] + xl);
-                d[i] = shift_in_from_left<C, NW>(d[i], prev);
-            } else if (CX[i] == -1) {
-                uint32_t next = wave_shl1(d[i].w[0]);
-                if constexpr (K::kBytes == 2) next &= 0xffffu;
-                if (right_edge) next = ld_elem<C>(src, rb[i] + xr);
-                d[i] = shift_in_from_right<C, NW>(d[i], next);
+        for (int k = 0; k < 5; ++k) {
+            const int i = kPlusX[k];  // c_x = +1: pull from x - 1
+            uint32_t prev = wave_shr1(d[i].w[NW - 1]);
+            if (left_edge) {
+                if (a.lds_edges) {
+                    prev = x0 == 0 ? edge_row_last[rit][k] : edge_wave_last[wave - 1][k];
+                } else {
+                    prev = ld_elem<C>(src, rb[i] + xl);
+                    if constexpr (K::kBytes == 2) prev <<= 16;  // as the upper half of a dword
+                }
             }
+            if constexpr (K::kBytes == 2) prev >>= 16;
+            d[i] = shift_in_from_left<C, NW>(d[i], prev);
+        }
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            const int i = kMinusX[k];  // c_x = -1: pull from x + 1
+            uint32_t next = wave_shl1(d[i].w[0]);
+            if (right_edge) {
+                if (a.lds_edges)
+                    next = x0 + V == nx ? edge_row_first[rit][k] : edge_wave_first[wave + 1][k];
+                else
+                    next = ld_elem<C>(src, rb[i] + xr);
+            }
+            if constexpr (K::kBytes == 2) next &= 0xffffu;
+            d[i] = shift_in_from_right<C, NW>(d[i], next);
         }
 
         // halfway bounce-back: where x - c_i is solid, take the site's own opp(i) value
