@@ -168,7 +168,7 @@ def sums(S, flags=None) -> np.ndarray:
     return out
 
 
-def run_window(rho, u, flags, tau, nsteps, centres, F=None):
+def run_window(rho, u, flags, tau, nsteps, centres, F=None, shape=None, fields=None):
     """Light-cone evaluation of single sites after ``nsteps`` steps.
 
     A site's value after n steps depends only on the initial state within
@@ -178,9 +178,12 @@ def run_window(rho, u, flags, tau, nsteps, centres, F=None):
     it is no wider than that), runs the oracle on the window alone and returns
     (rho, u) at the centre.  Errors from the window's own artificial wrap
     travel inward one site per step and reach distance n-1 from the edge at
-    most, so the centre is exact.  Returns rho[k], u[k, 3].
+    most, so the centre is exact.  The initial fields come either from full
+    arrays (rho, u, flags) or, with ``fields`` and ``shape`` = (nz, ny, nx),
+    from a function fields(iz, iy, ix) -> (rho, u) evaluated on the window's
+    periodic site indices (then flags is None).  Returns rho[k], u[k, 3].
     """
-    nz, ny, nx = rho.shape
+    nz, ny, nx = shape if shape is not None else rho.shape
     W = 2 * nsteps + 1
     out_r = np.empty(len(centres))
     out_u = np.empty((len(centres), 3))
@@ -195,9 +198,15 @@ def run_window(rho, u, flags, tau, nsteps, centres, F=None):
                 idx.append((np.arange(W) + c - nsteps) % n)
                 cen.append(nsteps)
         iz, iy, ix = np.ix_(*idx)
-        r_w = np.ascontiguousarray(rho[iz, iy, ix], dtype=np.float64)
-        u_w = np.ascontiguousarray(u[:, iz, iy, ix], dtype=np.float64)
-        f_w = None if flags is None else np.ascontiguousarray(flags[iz, iy, ix])
+        if fields is not None:
+            r_w, u_w = fields(iz.astype(np.float64), iy.astype(np.float64), ix.astype(np.float64))
+            r_w = np.ascontiguousarray(np.broadcast_to(r_w, (len(idx[0]), len(idx[1]), len(idx[2]))))
+            u_w = np.ascontiguousarray(np.broadcast_to(u_w, (3, len(idx[0]), len(idx[1]), len(idx[2]))))
+            f_w = None
+        else:
+            r_w = np.ascontiguousarray(rho[iz, iy, ix], dtype=np.float64)
+            u_w = np.ascontiguousarray(u[:, iz, iy, ix], dtype=np.float64)
+            f_w = None if flags is None else np.ascontiguousarray(flags[iz, iy, ix])
         S = init(r_w.shape, r_w, u_w, f_w)
         S = run(S, tau, nsteps, F=F, flags=f_w)
         r_o, u_o = macros(S, F=F, flags=f_w)

@@ -822,7 +822,7 @@ __global__ __launch_bounds__(kBlock) void step_site(StepArgs a)
 // Solid sites get zero macros in the one-site kernel (it skips them).
 __global__ __launch_bounds__(kBlock) void zero_solid_macros(const uint8_t *flags, int n, float *rho, float *u)
 {
-    for (int s = blockIdx.x * kBlock + threadIdx.x; s < n; s += gridDim.x * kBlock) {
+    for (int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x; s < n; s += (int64_t)gridDim.x * kBlock) {
         if (flags[s]) {
             rho[s] = 0.0f;
             u[s] = 0.0f;
@@ -841,7 +841,7 @@ __global__ __launch_bounds__(kBlock) void init_eq(InitArgs a)
     using K = Codec<C>;
     char *dst = reinterpret_cast<char *>(a.dst);
     const double w[3] = {1.0 / 3.0, 1.0 / 18.0, 1.0 / 36.0};
-    for (int s = blockIdx.x * kBlock + threadIdx.x; s < a.n; s += gridDim.x * kBlock) {
+    for (int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x; s < a.n; s += (int64_t)gridDim.x * kBlock) {
         const bool solid = a.flags && a.flags[s];
         const double rho = a.rho ? a.rho[s] : 1.0;
         const double ux = a.u ? a.u[s] : 0.0;
@@ -868,7 +868,7 @@ __global__ __launch_bounds__(kBlock) void macros_kernel(MacroArgs a)
 {
     using K = Codec<C>;
     const char *src = reinterpret_cast<const char *>(a.src);
-    for (int s = blockIdx.x * kBlock + threadIdx.x; s < a.n; s += gridDim.x * kBlock) {
+    for (int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x; s < a.n; s += (int64_t)gridDim.x * kBlock) {
         float r = 0.0f, ux = 0.0f, uy = 0.0f, uz = 0.0f;
         if (!(a.flags && a.flags[s])) {
             const uint32_t row = (uint32_t)s / a.lay.nx;
@@ -899,7 +899,7 @@ __global__ __launch_bounds__(kBlock) void macros_kernel(MacroArgs a)
 __global__ __launch_bounds__(kBlock) void build_masks(const uint8_t *flags, int nx, int ny, int nz, uint32_t *nbmask)
 {
     const int n = nx * ny * nz;
-    for (int s = blockIdx.x * kBlock + threadIdx.x; s < n; s += gridDim.x * kBlock) {
+    for (int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x; s < n; s += (int64_t)gridDim.x * kBlock) {
         const int x = s % nx, y = (s / nx) % ny, z = s / (nx * ny);
         uint32_t m = flags[s] ? (1u << 31) : 0u;
 #pragma unroll
@@ -916,7 +916,7 @@ __global__ __launch_bounds__(kBlock) void build_masks(const uint8_t *flags, int 
 
 __global__ __launch_bounds__(kBlock) void build_rowdirty(const uint32_t *nbmask, int nx, int nrows, uint8_t *rowdirty)
 {
-    for (int r = blockIdx.x * kBlock + threadIdx.x; r < nrows; r += gridDim.x * kBlock) {
+    for (int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x; r < nrows; r += (int64_t)gridDim.x * kBlock) {
         uint32_t any = 0;
         for (int x = 0; x < nx; ++x) any |= nbmask[(size_t)r * nx + x];
         rowdirty[r] = any ? 1 : 0;

@@ -88,6 +88,24 @@ def sphere_flags(nx: int, ny: int, nz: int, porosity: float, seed: int,
     return f
 
 
+def smooth_fields(xp, iz, iy, ix, n, amp: float = 0.02):
+    """Analytic smooth initial fields at integer site indices (any lattice size).
+
+    xp is numpy or torch; iz, iy, ix broadcastable index arrays (float64).
+    rho = 1 + amp/4 cos(phi_3), u_x = amp sin(phi_1), u_y = amp cos(phi_2),
+    u_z = amp sin(phi_3) with phases phi_k = 2 pi (a_k x + b_k y + c_k z) / n.
+    Evaluated identically on the host (numpy) and on the device (torch), so
+    a window of it can be rebuilt for the oracle without the whole field.
+    """
+    two_pi = 2.0 * math.pi / n
+    p1 = two_pi * (ix + 2 * iy + 3 * iz)
+    p2 = two_pi * (3 * ix + iy + 2 * iz)
+    p3 = two_pi * (2 * ix + 3 * iy + iz)
+    rho = 1.0 + 0.25 * amp * xp.cos(p3)
+    u = xp.stack([amp * xp.sin(p1), amp * xp.cos(p2), amp * xp.sin(p3)])
+    return rho, u
+
+
 # --- the named workloads -------------------------------------------------------
 
 def tgv_box(n: int = 32, u0: float = 0.01, tau: float = 0.8, steps: int = 200):

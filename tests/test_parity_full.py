@@ -1,0 +1,207 @@
+"""GPU parity at the full workload sizes, in the launch configuration bench.py times.
+
+* 512^3 Taylor-Green vortex, 1000 steps: a state uniform in z evolves exactly
+  as the nz = 1 lattice (every site does the same arithmetic; the oracle
+  checks this bit for bit), so the whole 512^3 field is compared with an FP64
+  oracle run on 512 x 512 x 1 sites.
+* 512^3 Taylor-Green vortex with seeded U(+-1e-3) velocity noise: sampled
+  sites after 16 steps against the light-cone oracle (a site after n steps
+  depends only on the initial state within distance n).
+* 256 x 128 x 128 channel, 5000 steps: sampled sites, the x-z averaged
+  profile and the conservation totals against stored FP64 oracle results
+  (tests/golden/channel256x128x128_5000.json, written by
+  tests/golden/make_channel_golden.py from the oracle alone).
+* Largest lattices: 1280^3 (2.1e9 sites, near the 2^31-site index limit) with
+  FP16 storage and 1024^3 with FP32 storage, sampled sites after 4 steps.
+
+Bounds: relative L2 error of u <= 1e-5 (FP32 storage) and <= 2e-3 (FP16);
+BF16 storage is measured and reported against a sanity bound.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2409_16781_amd as lbm
+from paper_2409_16781_amd import inputs
+from gpu_util import require_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TOL = {"f32": 1e-5, "f16": 2e-3, "bf16": 5e-2}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _setup():
+    require_gpu()
+    oracle.build(force=False)
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+# ----------------------------------------------- 512^3 TGV, 1000 steps -----
+
+@pytest.fixture(scope="module")
+def tgv512_ref():
+    n, tau, steps = 512, 0.55, 1000
+    r2, u2 = inputs.tgv_fields(n, n, 1, 0.01)
+    S = oracle.run(oracle.init((1, n, n), r2, u2), tau, steps)
+    _, u_ref = oracle.macros(S)
+    return dict(n=n, tau=tau, steps=steps, r2=r2, u2=u2, u_ref=u_ref[:, 0])
+
+
+@pytest.mark.parametrize("codec", ["f32", "f16", "bf16"])
+def test_tgv512_1000_steps_whole_field(tgv512_ref, codec):
+    torch = require_gpu()
+    c = tgv512_ref
+    n = c["n"]
+    say(f"[gpu] tgv512 z-uniform {codec} {c['steps']} steps")
+    lat = lbm.Lattice(n, n, n, c["tau"], codec=codec)
+    rho = torch.from_numpy(c["r2"]).cuda().expand(n, n, n).contiguous()
+    u = torch.from_numpy(c["u2"]).cuda().expand(3, n, n, n).contiguous()
+    lat.init_eq(rho, u)
+    del rho, u
+    lat.step(c["steps"])
+    sums = lat.sums(c["steps"])
+    r_g, u_g = lat.macros()
+    # every z plane is the same computation: bit-identical planes
+    assert torch.equal(u_g, u_g[:, :1].expand(3, n, n, n))
+    err = rel_l2(u_g[:, 0].double().cpu().numpy(), c["u_ref"])
+    drift = abs(sums[-1, 0] - sums[0, 0]) / sums[0, 0]
+    say(f"  rel-L2(u) = {err:.3e} over all {n}^3 sites; mass drift over {c['steps']} steps {drift:.2e}")
+    assert err <= TOL[codec]
+    lat.close()
+    torch.cuda.empty_cache()
+
+
+# ----------------------------------------- 512^3 TGV + noise, light cone -----
+
+@pytest.fixture(scope="module")
+def tgv512_noise():
+    return inputs.tgv_noise_box(512, u0=0.01, tau=0.55, steps=1000, noise=1e-3, seed=2)
+
+
+@pytest.mark.parametrize("codec", ["f32", "f16"])
+def test_tgv512_noise_sampled_sites(tgv512_noise, codec):
+    torch = require_gpu()
+    cfg = tgv512_noise
+    n, steps = 512, 16
+    say(f"[gpu] tgv512 + noise {codec}, {steps} steps, light-cone samples")
+    lat = lbm.Lattice(n, n, n, cfg["tau"], codec=codec)
+    lat.init_eq(torch.from_numpy(cfg["rho"]).cuda(), torch.from_numpy(cfg["u"]).cuda())
+    torch.cuda.empty_cache()
+    lat.step(steps)
+    r_g, u_g = lat.macros()
+    rng = np.random.default_rng(5)
+    centres = [tuple(int(v) for v in rng.integers(0, n, 3)) for _ in range(24)]
+    centres += [(0, 0, 0), (n - 1, n - 1, n - 1), (0, n - 1, 0), (n - 1, 0, n - 1)]
+    idx = torch.tensor(centres, device="cuda")
+    ug = u_g[:, idx[:, 0], idx[:, 1], idx[:, 2]].T.double().cpu().numpy()
+    rr, ur = oracle.run_window(cfg["rho"], cfg["u"], None, cfg["tau"], steps, centres)
+    err = rel_l2(ug, ur)
+    say(f"  rel-L2(u) over {len(centres)} sampled sites = {err:.3e}")
+    assert err <= TOL[codec]
+    lat.close()
+    torch.cuda.empty_cache()
+
+
+# --------------------------------------------- channel, 5000 steps ---------
+
+GOLDEN = os.path.join(HERE, "golden", "channel256x128x128_5000.json")
+
+
+@pytest.mark.skipif(not os.path.exists(GOLDEN), reason="golden channel results not generated")
+@pytest.mark.parametrize("codec", ["f32", "f16"])
+def test_channel_5000_steps_vs_stored_oracle(codec):
+    torch = require_gpu()
+    gold = json.load(open(GOLDEN))
+    cfg = inputs.channel(256, 128, 128, tau=0.6, g=1e-6, steps=5000, noise=1e-4, seed=1)
+    nz, ny, nx = cfg["shape"]
+    say(f"[gpu] channel 256x128x128 {codec} 5000 steps")
+    lat = lbm.Lattice(nx, ny, nz, cfg["tau"], flags=cfg["flags"], codec=codec)
+    lat.set_force(*cfg["force"])
+    lat.init_eq(torch.from_numpy(cfg["rho"]).cuda(), torch.from_numpy(cfg["u"]).cuda())
+    lat.step(gold["steps"])
+    sums = lat.sums(1)[0]
+    r_g, u_g = lat.macros()
+    idx = torch.tensor(gold["sites_zyx"], device="cuda")
+    ug = u_g[:, idx[:, 0], idx[:, 1], idx[:, 2]].T.double().cpu().numpy()
+    err = rel_l2(ug, np.array(gold["u"]))
+    prof = u_g[0].double().mean(dim=(0, 2)).cpu().numpy()
+    perr = rel_l2(prof[1:-1], np.array(gold["profile_ux"])[1:-1])
+    say(f"  rel-L2(u) sampled = {err:.3e}, profile = {perr:.3e}; mass {sums[0]:.10f} vs {gold['sums'][0]:.10f}")
+    assert err <= TOL[codec]
+    assert perr <= TOL[codec]
+    assert abs(sums[0] - gold["sums"][0]) < (1e-6 if codec == "f32" else 1e-2)
+    lat.close()
+    torch.cuda.empty_cache()
+
+
+def test_channel_full_size_light_cone():
+    """The 256x128x128 channel with walls and force, sampled after 40 steps
+    against the light-cone oracle (independent of the stored results)."""
+    torch = require_gpu()
+    cfg = inputs.channel(256, 128, 128, tau=0.6, g=1e-6, steps=40, noise=1e-4, seed=1)
+    nz, ny, nx = cfg["shape"]
+    steps = 40
+    lat = lbm.Lattice(nx, ny, nz, cfg["tau"], flags=cfg["flags"], codec="f32")
+    lat.set_force(*cfg["force"])
+    lat.init_eq(torch.from_numpy(cfg["rho"]).cuda(), torch.from_numpy(cfg["u"]).cuda())
+    lat.step(steps)
+    _, u_g = lat.macros()
+    rng = np.random.default_rng(6)
+    centres = [(int(rng.integers(0, nz)), int(rng.integers(1, ny - 1)), int(rng.integers(0, nx))) for _ in range(6)]
+    centres += [(0, 1, 0), (nz - 1, ny - 2, nx - 1)]
+    idx = torch.tensor(centres, device="cuda")
+    ug = u_g[:, idx[:, 0], idx[:, 1], idx[:, 2]].T.double().cpu().numpy()
+    _, ur = oracle.run_window(cfg["rho"], cfg["u"], cfg["flags"], cfg["tau"], steps, centres, F=cfg["force"])
+    err = rel_l2(ug, ur)
+    say(f"  channel light-cone rel-L2(u) = {err:.3e}")
+    assert err <= 1e-5
+    lat.close()
+
+
+# ------------------------------------------------- largest lattices --------
+
+@pytest.mark.parametrize("codec,n", [("f16", 1280), ("f32", 1024)])
+def test_largest_lattice_sampled_sites(codec, n):
+    torch = require_gpu()
+    steps = 4
+    say(f"[gpu] {n}^3 {codec} ({n ** 3 / 1e9:.2f}e9 sites), {steps} steps")
+    lat = lbm.Lattice(n, n, n, 0.7, codec=codec)
+    lat.set_force(2e-5, -1e-5, 5e-6)
+    ar = torch.arange(n, device="cuda", dtype=torch.float64)
+    # analytic initial fields evaluated on the device plane by plane
+    u = torch.empty((3, n, n, n), dtype=torch.float64, device="cuda")
+    rho = torch.empty((n, n, n), dtype=torch.float64, device="cuda")
+    for z in range(n):
+        r_z, u_z = inputs.smooth_fields(torch, torch.tensor(float(z), device="cuda", dtype=torch.float64),
+                                        ar[:, None], ar[None, :], n)
+        rho[z] = r_z
+        u[:, z] = u_z
+    lat.init_eq(rho, u)
+    del rho, u
+    torch.cuda.empty_cache()
+    lat.step(steps)
+    sums = lat.sums(steps)
+    assert np.all(np.isfinite(sums))
+    r_g, u_g = lat.macros()
+    centres = [(0, 0, 0), (n - 1, n - 1, n - 1), (n // 2, 3, n - 2), (7, n // 3, 11), (n - 3, n // 2, n // 2)]
+    idx = torch.tensor(centres, device="cuda")
+    ug = u_g[:, idx[:, 0], idx[:, 1], idx[:, 2]].T.double().cpu().numpy()
+    _, ur = oracle.run_window(None, None, None, 0.7, steps, centres, F=(2e-5, -1e-5, 5e-6), shape=(n, n, n),
+                              fields=lambda iz, iy, ix: inputs.smooth_fields(np, iz, iy, ix, n))
+    err = rel_l2(ug, ur)
+    say(f"  rel-L2(u) sampled = {err:.3e}")
+    assert err <= TOL[codec]
+    lat.close()
+    del r_g, u_g
+    torch.cuda.empty_cache()
