@@ -50,6 +50,25 @@ def workload_fields(n):
     return cfg
 
 
+def measured_traffic(codec, n):
+    """HBM bytes per step-kernel launch from the committed rocprofv3 counters
+    (FETCH_SIZE and WRITE_SIZE, each scaled by what it reads for a copy of
+    known size), or None when the kernel source changed since they were taken
+    or the lattice differs."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(here, "profiles", "step_vec_512cube_tgv.traffic.json")
+    src = os.path.join(here, "paper_2409_16781_amd", "csrc", "lb_kernels.hip")
+    try:
+        tr = json.load(open(path))
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if n != 512 or tr.get("kernel_source_sha256") != digest:
+        return None
+    return tr["per_launch_bytes"].get(codec)
+
+
 def bytes_per_site(codec):
     return 19 * 2 * (4 if codec == "f32" else 2)
 
@@ -146,6 +165,8 @@ def main():
     main_codec = "f32" if "f32" in results else list(results)[0]
     m = results[main_codec]
     N = n ** 3
+    traffic_bytes = measured_traffic(main_codec, n)
+    traffic_gbs = None if traffic_bytes is None else traffic_bytes / (m["step_kernel_ms"] * 1e-3) / 1e9
     line = {
         "metric": "D3Q19 MLUPS & % HBM peak at 512³: FP32 vs FP16-store, equal-accuracy",
         "value": round(m["mlups"], 1),
@@ -163,7 +184,10 @@ def main():
                                f"velocity noise, tau=0.55, {main_codec} storage, FP64 GPU totals per step",
                    "sites": N, "storage": main_codec, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(m["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(m["frac_hbm"], 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(m["frac_hbm"], 4),
+                     "traffic": None if traffic_gbs is None else round(traffic_gbs, 1),
+                     "traffic_bytes_per_launch": traffic_bytes,
+                     "traffic_bytes_per_site": None if traffic_bytes is None else round(traffic_bytes / N, 2),
                      "bytes_per_site": bytes_per_site(main_codec), "kernel_ms": round(m["step_kernel_ms"], 4),
                      "kernel": "step_vec (fused pull-stream + BGK/Guo collide)",
                      "copy_ceiling_gbs": round(m["copy_gbs"], 1), "frac_of_copy": round(m["frac_copy"], 4)},
