@@ -38,7 +38,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=20)
     p.add_argument("--n", type=int, default=512, help="lattice edge (default 512)")
     p.add_argument("--codecs", default="f32,f16,bf16")
-    p.add_argument("--cpu-steps", type=int, default=3, help="oracle steps in the CPU baseline sample")
+    p.add_argument("--cpu-steps", type=int, default=5, help="oracle steps in the CPU baseline sample")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
     p.add_argument("--reps", type=int, default=3, help="timed repetitions (median reported)")
     return p.parse_args()
