@@ -41,6 +41,8 @@ def parse():
     p.add_argument("--cpu-steps", type=int, default=5, help="oracle steps in the CPU baseline sample")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
     p.add_argument("--reps", type=int, default=3, help="timed repetitions (median reported)")
+    p.add_argument("--no-batch", action="store_true", help="skip the 64-domain batch leg")
+    p.add_argument("--batch-steps", type=int, default=500, help="timed steps of the batch leg")
     return p.parse_args()
 
 
@@ -115,6 +117,37 @@ def run_codec(torch, lbm, cfg, codec, steps, warmup, reps):
                grid=lat.info["grid"], steps_done=lat.steps_done)
     lat.close()
     return res, u_out
+
+
+def run_batch(torch, lbm, steps, reps):
+    """64 porous channel domains (extents U{16..96}, porosity 0.8, tau
+    U[0.55, 1.0], force 1e-6) advanced by one launch per step in the
+    autotuned launch shape."""
+    from paper_2409_16781_amd import inputs
+    doms = inputs.batch_domains(64, seed=3)
+    b = lbm.Batch([(d["shape"][2], d["shape"][1], d["shape"][0]) for d in doms], [d["tau"] for d in doms],
+                  flags=[d["flags"] for d in doms], codec="f32", autotune=True)
+    for k, d in enumerate(doms):
+        b.set_force(*d["force"], domain=k)
+        b.init_eq(k, torch.from_numpy(d["rho"]).cuda(), torch.from_numpy(d["u"]).cuda())
+    info = b.info
+    b.step(20)
+    b.sync()
+    ms = sorted(b.time_steps(steps) for _ in range(reps))[reps // 2]
+    kernel_ms = b.time_step_kernel(50)
+    fluid, sites = info["fluid_sites"], info["sites"]
+    gbs = 152.0 * fluid / (kernel_ms * 1e-3) / 1e9
+    sums = b.sums(0, 1)
+    b.close()
+    return dict(workload="64 D3Q19 porous channel domains, extents U{16..96} per axis (seed 3), walls y=0/ny-1 + "
+                         "spheres r~U[2,6] to porosity 0.8, tau~U[0.55,1.0], force 1e-6, FP32 storage",
+                domains=64, sites=sites, fluid_sites=fluid, steps=steps, ms_per_step=round(ms, 5),
+                mlups_fluid=round(fluid / (ms * 1e-3) / 1e6, 1), mlups_all_sites=round(sites / (ms * 1e-3) / 1e6, 1),
+                kernel_ms=round(kernel_ms, 5), achieved_gbs_fluid=round(gbs, 1),
+                frac_hbm=round(gbs / HBM_PEAK_GBS, 4), bytes_per_fluid_site=152,
+                shape={k: info[k] for k in ("variant", "sites_per_lane", "grid", "tiles", "tile_order", "seg_bytes",
+                                             "grid_mult", "autotuned")},
+                finite_totals=bool(np.all(np.isfinite(sums))))
 
 
 def cpu_baseline(cfg, steps):
@@ -196,6 +229,11 @@ def main():
     }
     if "f16" in results and "f32" in results:
         line["f16_over_f32_mlups"] = round(results["f16"]["mlups"] / results["f32"]["mlups"], 3)
+    if not args.no_batch:
+        log("[bench] batch of 64 porous domains (autotuned)")
+        line["batch64"] = run_batch(torch, lbm, args.batch_steps, args.reps)
+        log(f"[bench] batch64: {line['batch64']['mlups_fluid']:.0f} fluid MLUPS, "
+            f"{line['batch64']['achieved_gbs_fluid']:.0f} GB/s")
     if not args.no_cpu:
         log(f"[bench] CPU baseline: oracle, {args.cpu_steps} steps")
         line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_steps)

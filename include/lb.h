@@ -149,7 +149,8 @@ int lb_sums(lb_lattice *lat, double *out, int k);
  * (float for LB_F32, IEEE binary16 for LB_F16S, bfloat16 for LB_BF16S).
  * bytes must equal 19 * N * (4 or 2).  where is LB_HOST or LB_DEVICE.
  * Host copies synchronise; device copies are enqueued.  lb_set_f leaves the
- * step count unchanged.  Values at solid sites are carried but never used.
+ * step count unchanged.  Values at solid sites are not part of the state: no
+ * step reads them, and a step writes zero there (or leaves them unchanged).
  */
 int lb_get_f(lb_lattice *lat, void *buf, size_t bytes, int where);
 int lb_set_f(lb_lattice *lat, const void *buf, size_t bytes, int where);
@@ -198,6 +199,86 @@ int lb_time_step_kernel(lb_lattice *lat, int n, double *ms);
  * array, so the state is unchanged.
  */
 int lb_copy_probe(lb_lattice *lat, int reps, double *ms);
+
+/* ---- batches of lattices ------------------------------------------------- */
+
+/*
+ * A batch holds `count` independent lattices ("domains") with their own
+ * extents, relaxation times, solid flags and body forces, and advances all of
+ * them together: one kernel launch per step covers every site of every domain
+ * (the fused update of Section 3.1 applied to each domain exactly as
+ * lb_step applies it to one lattice, with the same D3Q19 set, bounce-back,
+ * periodic faces and Guo force).  Domains never exchange data.
+ * Sites, population order, storage codecs and the raw-state format are those
+ * of the single-lattice calls above, per domain.
+ */
+typedef struct lb_batch lb_batch;
+
+/*
+ * Create a batch.  dims: HOST int[3 * count], (nx, ny, nz) of domain d at
+ * 3d..3d+2, each >= 1.  taus: HOST double[count], each > 0.5 or +INFINITY.
+ * flags: NULL (every domain all fluid) or a HOST array of count pointers,
+ * each NULL (all fluid) or nx*ny*nz bytes of 0 (fluid) / 1 (solid), copied.
+ * storage: LB_F32, LB_F16S or LB_BF16S.  hip_stream: a borrowed hipStream_t
+ * or NULL for a stream the batch creates.  autotune: 0 = the default launch
+ * shape (16-byte vectors of population rows, storage blocks of 32 KiB per
+ * population, one workgroup per tile); 1 = time every candidate shape (sites
+ * per lane, storage block size, grid size, tile order) on this batch once
+ * and keep the fastest (results are remembered for the rest of the process,
+ * keyed by the codec and the domains' extents).  Every domain starts at rest
+ * with zero force; every step counter is 0.  All device memory is allocated
+ * here and owned by the batch.  Returns NULL on failure (lb_last_error()).
+ */
+lb_batch *lb_batch_create(int count, const int *dims, const double *taus, const uint8_t *const *flags, int storage,
+                          void *hip_stream, int autotune);
+
+/* Free every resource of the batch (after waiting for its stream).  NULL is a no-op. */
+void lb_batch_destroy(lb_batch *b);
+
+/* Uniform force density of domain d (d = -1: every domain); as lb_set_force.
+ * Synchronises the batch's stream. */
+int lb_batch_set_force(lb_batch *b, int d, double fx, double fy, double fz);
+
+/* Equilibrium initial state of domain d from caller-owned DEVICE FP64 fields
+ * (N and 3N doubles of that domain, NULL = 1 and 0); as lb_init_eq. */
+int lb_batch_init_eq(lb_batch *b, int d, const double *rho, const double *u);
+
+/* Enqueue n >= 0 steps of every domain (asynchronous). */
+int lb_batch_step(lb_batch *b, int n);
+
+/* Density and velocity of domain d into caller-owned DEVICE buffers (N and
+ * 3N floats of that domain, either may be NULL); as lb_macros.  Enqueued. */
+int lb_batch_macros(lb_batch *b, int d, float *rho, float *u);
+
+/* FP64 {mass, momentum x, y, z} of the fluid sites of domain d after each of
+ * the last k steps (out: 4k doubles, oldest first); as lb_sums. */
+int lb_batch_sums(lb_batch *b, int d, double *out, int k);
+
+/* Raw state of domain d in storage format (19 planes of that domain's N
+ * elements); as lb_get_f / lb_set_f.  Host copies synchronise. */
+int lb_batch_get_f(lb_batch *b, int d, void *buf, size_t bytes, int where);
+int lb_batch_set_f(lb_batch *b, int d, const void *buf, size_t bytes, int where);
+
+/* Wait for all work enqueued on the batch's stream. */
+int lb_batch_sync(lb_batch *b);
+
+/* Steps taken by the batch (every domain takes the same steps); -1 for a bad handle. */
+long long lb_batch_steps_done(lb_batch *b);
+
+/*
+ * Integer properties: key 0 = kernel variant (1 / 2 / 3 = 16- / 8- / 4-byte
+ * vectors per lane and population), 1 = sites per lane, 2 = workgroups per
+ * step launch, 3 = tiles of 256 lanes over all domains, 4 = tile order, 5 =
+ * domains, 6 = sites of all domains, 7 = fluid sites of all domains, 8 =
+ * bytes of both population arrays of all domains, 9 = target bytes of one
+ * population in a storage block, 10 = grid multiple (0: one workgroup per
+ * tile), 11 = 1 if the shape was chosen by the autotuner.  -1 on error.
+ */
+long long lb_batch_query(lb_batch *b, int key);
+
+/* Measurement helpers, as lb_time_steps / lb_time_step_kernel (the state advances). */
+int lb_batch_time_steps(lb_batch *b, int n, double *ms);
+int lb_batch_time_step_kernel(lb_batch *b, int n, double *ms);
 
 #ifdef __cplusplus
 }

@@ -46,6 +46,20 @@ _SIGNATURES = {
     "lb_time_steps": (ctypes.c_int, [_P, ctypes.c_int, _P]),
     "lb_time_step_kernel": (ctypes.c_int, [_P, ctypes.c_int, _P]),
     "lb_copy_probe": (ctypes.c_int, [_P, ctypes.c_int, _P]),
+    "lb_batch_create": (_P, [ctypes.c_int, _P, _P, _P, ctypes.c_int, _P, ctypes.c_int]),
+    "lb_batch_destroy": (None, [_P]),
+    "lb_batch_set_force": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
+    "lb_batch_init_eq": (ctypes.c_int, [_P, ctypes.c_int, _P, _P]),
+    "lb_batch_step": (ctypes.c_int, [_P, ctypes.c_int]),
+    "lb_batch_macros": (ctypes.c_int, [_P, ctypes.c_int, _P, _P]),
+    "lb_batch_sums": (ctypes.c_int, [_P, ctypes.c_int, _P, ctypes.c_int]),
+    "lb_batch_get_f": (ctypes.c_int, [_P, ctypes.c_int, _P, ctypes.c_size_t, ctypes.c_int]),
+    "lb_batch_set_f": (ctypes.c_int, [_P, ctypes.c_int, _P, ctypes.c_size_t, ctypes.c_int]),
+    "lb_batch_sync": (ctypes.c_int, [_P]),
+    "lb_batch_steps_done": (ctypes.c_longlong, [_P]),
+    "lb_batch_query": (ctypes.c_longlong, [_P, ctypes.c_int]),
+    "lb_batch_time_steps": (ctypes.c_int, [_P, ctypes.c_int, _P]),
+    "lb_batch_time_step_kernel": (ctypes.c_int, [_P, ctypes.c_int, _P]),
 }
 
 _lib = None
@@ -223,6 +237,144 @@ class Lattice:
     def copy_probe(self, reps: int = 10) -> float:
         ms = ctypes.c_double(0.0)
         _check(lib().lb_copy_probe(self._h, int(reps), ctypes.byref(ms)), "lb_copy_probe")
+        return ms.value
+
+
+class Batch:
+    """Many independent D3Q19 lattices advanced by one kernel launch per step.
+
+    ``dims``: list of (nx, ny, nz); ``taus``: one relaxation time per domain;
+    ``flags``: None or a list with one (nz, ny, nx) uint8 array (or None) per
+    domain; ``autotune``: time the candidate launch shapes once and keep the
+    fastest.  Per-domain arrays follow the ``Lattice`` conventions.
+    """
+
+    def __init__(self, dims, taus, flags=None, codec: str = "f32", stream=None, autotune: bool = False):
+        import torch
+
+        if codec not in CODECS:
+            raise ValueError(f"codec must be one of {sorted(CODECS)}")
+        self.codec = codec
+        self.dims = [tuple(int(v) for v in d) for d in dims]
+        self.count = len(self.dims)
+        if len(taus) != self.count:
+            raise ValueError("one tau per domain")
+        dims_arr = np.ascontiguousarray(np.array(self.dims, dtype=np.int32).reshape(-1))
+        tau_arr = np.ascontiguousarray(np.array(taus, dtype=np.float64))
+        self._keep = [dims_arr, tau_arr]
+        fl_ptrs = None
+        if flags is not None:
+            if len(flags) != self.count:
+                raise ValueError("one flag array (or None) per domain")
+            arrs = []
+            ptrs = (ctypes.c_void_p * self.count)()
+            for k, (f, (nx, ny, nz)) in enumerate(zip(flags, self.dims)):
+                if f is None:
+                    ptrs[k] = None
+                    continue
+                a = np.ascontiguousarray(f, dtype=np.uint8)
+                if a.shape != (nz, ny, nx):
+                    raise ValueError(f"flags of domain {k} must have shape {(nz, ny, nx)}")
+                arrs.append(a)
+                ptrs[k] = a.ctypes.data_as(ctypes.c_void_p)
+            self._keep += [arrs, ptrs]
+            fl_ptrs = ctypes.cast(ptrs, ctypes.c_void_p)
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        h = lib().lb_batch_create(self.count, dims_arr.ctypes.data_as(ctypes.c_void_p),
+                                  tau_arr.ctypes.data_as(ctypes.c_void_p), fl_ptrs, CODECS[codec],
+                                  ctypes.c_void_p(self._stream.cuda_stream), 1 if autotune else 0)
+        if not h:
+            raise LBError(LB_EINVAL, "lb_batch_create", last_error())
+        self._h = ctypes.c_void_p(h)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().lb_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _shape(self, d):
+        nx, ny, nz = self.dims[d]
+        return nz, ny, nx
+
+    def set_force(self, fx: float, fy: float = 0.0, fz: float = 0.0, domain: int = -1):
+        _check(lib().lb_batch_set_force(self._h, int(domain), float(fx), float(fy), float(fz)), "lb_batch_set_force")
+
+    def init_eq(self, d: int, rho=None, u=None):
+        import torch
+
+        shp = self._shape(d)
+        for t, shape in ((rho, shp), (u, (3,) + shp)):
+            if t is not None:
+                if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != shape:
+                    raise ValueError(f"expected a contiguous float64 CUDA tensor of shape {shape}")
+        _check(lib().lb_batch_init_eq(self._h, int(d), _ptr(rho), _ptr(u)), "lb_batch_init_eq")
+
+    def step(self, n: int = 1):
+        _check(lib().lb_batch_step(self._h, int(n)), "lb_batch_step")
+
+    def macros(self, d: int):
+        import torch
+
+        shp = self._shape(d)
+        rho = torch.empty(shp, dtype=torch.float32, device="cuda")
+        u = torch.empty((3,) + shp, dtype=torch.float32, device="cuda")
+        _check(lib().lb_batch_macros(self._h, int(d), _ptr(rho), _ptr(u)), "lb_batch_macros")
+        return rho, u
+
+    def sums(self, d: int, k: int = 1) -> np.ndarray:
+        out = np.zeros((k, 4), dtype=np.float64)
+        rc = lib().lb_batch_sums(self._h, int(d), out.ctypes.data_as(ctypes.c_void_p), int(k))
+        if rc == LB_EUNSTABLE:
+            raise LBError(rc, "lb_batch_sums", last_error())
+        _check(rc, "lb_batch_sums")
+        return out
+
+    def _raw_dtype(self):
+        return np.float32 if self.codec == "f32" else np.uint16
+
+    def get_f(self, d: int) -> np.ndarray:
+        out = np.empty((19,) + self._shape(d), dtype=self._raw_dtype())
+        _check(lib().lb_batch_get_f(self._h, int(d), out.ctypes.data_as(ctypes.c_void_p), out.nbytes, LB_HOST),
+               "lb_batch_get_f")
+        return out
+
+    def set_f(self, d: int, f: np.ndarray):
+        f = np.ascontiguousarray(f, dtype=self._raw_dtype())
+        if f.shape != (19,) + self._shape(d):
+            raise ValueError("state must have shape (19, nz, ny, nx)")
+        _check(lib().lb_batch_set_f(self._h, int(d), f.ctypes.data_as(ctypes.c_void_p), f.nbytes, LB_HOST),
+               "lb_batch_set_f")
+
+    def sync(self):
+        _check(lib().lb_batch_sync(self._h), "lb_batch_sync")
+
+    @property
+    def steps_done(self) -> int:
+        return int(lib().lb_batch_steps_done(self._h))
+
+    def query(self, key: int) -> int:
+        return int(lib().lb_batch_query(self._h, int(key)))
+
+    @property
+    def info(self) -> dict:
+        keys = ["variant", "sites_per_lane", "grid", "tiles", "tile_order", "domains", "sites", "fluid_sites",
+                "array_bytes", "seg_bytes", "grid_mult", "autotuned"]
+        return {k: self.query(i) for i, k in enumerate(keys)}
+
+    def time_steps(self, n: int) -> float:
+        ms = ctypes.c_double(0.0)
+        _check(lib().lb_batch_time_steps(self._h, int(n), ctypes.byref(ms)), "lb_batch_time_steps")
+        return ms.value
+
+    def time_step_kernel(self, n: int) -> float:
+        ms = ctypes.c_double(0.0)
+        _check(lib().lb_batch_time_step_kernel(self._h, int(n), ctypes.byref(ms)), "lb_batch_time_step_kernel")
         return ms.value
 
 

@@ -21,7 +21,7 @@
 
 using namespace lbm;
 
-namespace {
+namespace lbm {
 
 thread_local std::string g_err;
 
@@ -36,22 +36,21 @@ int fail(int code, const char *fmt, ...)
     return code;
 }
 
-#define HIP_OR_FAIL(expr)                                                                         \
-    do {                                                                                          \
-        hipError_t e_ = (expr);                                                                   \
-        if (e_ != hipSuccess) return fail(LB_EHIP, "%s: %s", #expr, hipGetErrorString(e_));       \
-    } while (0)
-
-constexpr uint64_t kMagic = 0x4c42443351313921ull;  // "LBD3Q19!"
-constexpr uint64_t kDead = 0xdeadd3a1deadd3a1ull;
-constexpr int kGraphSteps = 32;  // steps per captured graph (even: the graph ends on its start parity)
-
 long env_long(const char *name, long dflt)
 {
     const char *v = getenv(name);
     if (!v || !*v) return dflt;
     return strtol(v, nullptr, 10);
 }
+
+}  // namespace lbm
+
+namespace {
+
+constexpr uint64_t kMagic = 0x4c42443351313921ull;  // "LBD3Q19!"
+constexpr uint64_t kDead = 0xdeadd3a1deadd3a1ull;
+constexpr int kGraphSteps = 32;  // steps per captured graph (even: the graph ends on its start parity)
+
 
 }  // namespace
 
@@ -65,6 +64,7 @@ struct lb_lattice {
     double tau, omega;
     double force[3];
     void *buf[2];
+    void *alloc[2];   // allocations holding buf[0], buf[1] (buf[b] may sit at an offset)
     int cur;          // buf[cur] holds the state
     uint8_t *flags;   // device copy, or nullptr when all fluid
     uint32_t *nbmask;
@@ -79,6 +79,7 @@ struct lb_lattice {
     hipStream_t stream;
     hipStream_t cap_stream;
     int variant, vsites, grid, cus;
+    int tile_order;
     long long steps;
     hipGraphExec_t gexec;
     bool graph_ok;
@@ -104,13 +105,14 @@ StepArgs step_args(const lb_lattice *h, int from, float *rho, float *u)
     a.nslots = (int)(h->n / (uint64_t)h->vsites);
     // tiles of kBlock lanes hold whole rows when the lanes per row divide kBlock
     const int row_lanes = h->nx / h->vsites;
+    a.tile_order = h->tile_order;
     a.lds_edges = (h->variant != 0 && h->nx % h->vsites == 0 && row_lanes <= kBlock && (kBlock % row_lanes) == 0 &&
                    env_long("LB_LDS_EDGES", 1) != 0)
                       ? 1
                       : 0;
     a.lg_row_lanes = 0;
     while ((1 << a.lg_row_lanes) < row_lanes) ++a.lg_row_lanes;
-    a.div_nx = make_fastdiv((uint32_t)h->nx);
+    a.div_pitch = make_fastdiv((uint32_t)h->nx);
     a.div_ny = make_fastdiv((uint32_t)h->ny);
     a.coll = make_coll((float)h->omega, (float)h->force[0], (float)h->force[1], (float)h->force[2]);
     a.nbmask = h->nbmask;
@@ -209,7 +211,7 @@ void release(lb_lattice *h)
 {
     if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
-    void *ptrs[] = {h->buf[0],  h->buf[1],    h->flags,     h->nbmask, h->rowdirty,
+    void *ptrs[] = {h->alloc[0], h->alloc[1], h->flags,     h->nbmask, h->rowdirty,
                     h->partials, h->gpartials, h->ticket, h->ring,     h->counter};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -287,8 +289,16 @@ int create_impl(lb_lattice **out, int nx, int ny, int nz, double tau, const uint
     uint32_t lg = 0;
     while ((1l << lg) < rows) ++lg;
     h->lay.nx = (uint32_t)nx;
+    h->lay.pitch = (uint32_t)nx;
     h->lay.lg_r = lg;
-    h->lay.seg = (uint64_t)rows * nx;
+    // LB_SEG_PAD elements (a multiple of 128, so every vector stays aligned)
+    // between the population segments of a block, for tuning
+    const long seg_pad = env_long("LB_SEG_PAD", 0);
+    if (seg_pad < 0 || seg_pad % 128 != 0) {
+        delete h;
+        return fail(LB_EINVAL, "LB_SEG_PAD must be a non-negative multiple of 128");
+    }
+    h->lay.seg = (uint64_t)rows * nx + (uint64_t)seg_pad;
     h->lay.blk = (uint64_t)kQ * h->lay.seg;
     const uint64_t nblocks = (nrows + rows - 1) / rows;
     h->arr_elems = nblocks * h->lay.blk;
@@ -315,10 +325,17 @@ int create_impl(lb_lattice **out, int nx, int ny, int nz, double tau, const uint
         return fail(code, "%s: %s", what, hipGetErrorString(e));
     };
     const size_t pbytes = (size_t)h->arr_elems * h->esize;
+    // LB_AB_OFFSET bytes (a multiple of 256) in front of the second array, for
+    // tuning the relative placement of the two arrays in the HBM channels
+    const long ab_off = env_long("LB_AB_OFFSET", 0);
+    if (ab_off < 0 || ab_off % 256 != 0) return bail(LB_EINVAL, "LB_AB_OFFSET", hipErrorInvalidValue);
+    h->tile_order = env_long("LB_TILE_ORDER", 0) != 0 ? 1 : 0;
     hipError_t e;
     for (int b = 0; b < 2; ++b) {
-        e = hipMalloc(&h->buf[b], pbytes);
+        const size_t off = b == 1 ? (size_t)ab_off : 0;
+        e = hipMalloc(&h->alloc[b], pbytes + off);
         if (e != hipSuccess) return bail(LB_ENOMEM, "hipMalloc(populations)", e);
+        h->buf[b] = static_cast<char *>(h->alloc[b]) + off;
         e = hipMemsetAsync(h->buf[b], 0, pbytes, h->stream);
         if (e != hipSuccess) return bail(LB_EHIP, "hipMemsetAsync", e);
     }
@@ -337,7 +354,7 @@ int create_impl(lb_lattice **out, int nx, int ny, int nz, double tau, const uint
         if ((e = hipMalloc(&h->nbmask, n * sizeof(uint32_t) + 64)) != hipSuccess) return bail(LB_ENOMEM, "hipMalloc(masks)", e);
         if ((e = hipMalloc(&h->rowdirty, (size_t)ny * nz)) != hipSuccess) return bail(LB_ENOMEM, "hipMalloc(rows)", e);
         if ((e = hipMemcpyAsync(h->flags, flags, n, hipMemcpyHostToDevice, h->stream)) != hipSuccess) return bail(LB_EHIP, "hipMemcpyAsync(flags)", e);
-        if ((e = launch_masks(h->flags, nx, ny, nz, h->nbmask, h->rowdirty, h->stream)) != hipSuccess) return bail(LB_EHIP, "mask kernels", e);
+        if ((e = launch_masks(h->flags, nx, ny, nz, nx, h->nbmask, h->rowdirty, h->stream)) != hipSuccess) return bail(LB_EHIP, "mask kernels", e);
     }
     if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return bail(LB_EHIP, "hipStreamSynchronize", e);
     h->magic = kMagic;
@@ -470,8 +487,9 @@ static int copy_f(lb_lattice *h, void *host_or_dev, size_t bytes, int where, boo
     // population i: full blocks as one 2-D copy (R rows per block), then the
     // rows of a last, partly filled block
     const size_t es = (size_t)h->esize;
-    const size_t seg = h->lay.seg * es, blk = h->lay.blk * es, plane = h->n * es;
     const uint64_t rows = 1ull << h->lay.lg_r;
+    const size_t seg = h->lay.seg * es, blk = h->lay.blk * es, plane = h->n * es;
+    const size_t width = (size_t)rows * h->nx * es;  // bytes of one population in a full block
     const uint64_t nrows = (uint64_t)h->ny * h->nz;
     const uint64_t nfull = nrows / rows;
     const size_t tail = (size_t)(nrows - nfull * rows) * h->nx * es;
@@ -484,13 +502,13 @@ static int copy_f(lb_lattice *h, void *host_or_dev, size_t bytes, int where, boo
         char *usr = user + (size_t)i * plane;
         if (nfull > 0) {
             if (to_lattice)
-                HIP_OR_FAIL(hipMemcpy2DAsync(lat, blk, usr, seg, seg, nfull, kind, h->stream));
+                HIP_OR_FAIL(hipMemcpy2DAsync(lat, blk, usr, width, width, nfull, kind, h->stream));
             else
-                HIP_OR_FAIL(hipMemcpy2DAsync(usr, seg, lat, blk, seg, nfull, kind, h->stream));
+                HIP_OR_FAIL(hipMemcpy2DAsync(usr, width, lat, blk, width, nfull, kind, h->stream));
         }
         if (tail > 0) {
             char *lt = lat + nfull * blk;
-            char *ut = usr + nfull * seg;
+            char *ut = usr + nfull * width;
             HIP_OR_FAIL(hipMemcpyAsync(to_lattice ? lt : ut, to_lattice ? ut : lt, tail, kind, h->stream));
         }
     }

@@ -31,18 +31,22 @@ inline FastDiv make_fastdiv(uint32_t d)
 // Storage layout of one population array.  The ny*nz x-rows are grouped in
 // blocks of R = 2^lg_r consecutive rows (row r = y + ny z); inside a block each
 // population keeps its R rows contiguous, one population after the other:
-//   element (i, x, r) at (r >> lg_r) * 19 R nx + i * R nx + (r & (R - 1)) * nx + x.
+//   element (i, x, r) at (r >> lg_r) * blk + i * seg + (r & (R - 1)) * pitch + x,
+// with seg >= R * pitch and blk = 19 seg.  A row occupies pitch >= nx elements
+// (pitch > nx only in batches, where rows are padded to whole vectors).
 // R = 1 stores the 19 populations of a row one after the other; R >= ny*nz is
 // plain structure of arrays.  Blocks of tens of KiB per population keep the
 // 38 streams of a step close together in HBM.
 struct Layout {
-    uint32_t nx;
+    uint32_t nx;     // sites per row
+    uint32_t pitch;  // elements per stored row
     uint32_t lg_r;   // log2(rows per block)
-    uint64_t seg;    // R * nx: elements of one population in one block
-    uint64_t blk;    // 19 * R * nx: elements of one block
+    uint32_t pad_;
+    uint64_t seg;    // elements of one population in one block
+    uint64_t blk;    // 19 * seg: elements of one block
     __host__ __device__ uint64_t row_base(uint32_t r) const
     {
-        return (uint64_t)(r >> lg_r) * blk + (uint64_t)(r & ((1u << lg_r) - 1u)) * nx;
+        return (uint64_t)(r >> lg_r) * blk + (uint64_t)(r & ((1u << lg_r) - 1u)) * pitch;
     }
 };
 
@@ -68,16 +72,48 @@ struct StepArgs {
     void *dst;                // new state
     Layout lay;
     int nx, ny, nz;
-    int nslots;               // N / sites_per_thread
+    int nslots;               // rows * pitch / sites_per_thread
     int lds_edges;            // 1: every tile holds whole x-rows (x-edge elements via LDS)
     int lg_row_lanes;         // log2(lanes per x-row) when lds_edges
-    FastDiv div_nx, div_ny;
+    int tile_order;           // 0: tile = workgroup index; 1: contiguous tile ranges per XCD
+    FastDiv div_pitch, div_ny;
     Coll coll;
     const uint32_t *nbmask;   // per site: bit i = site x - c_i is solid, bit 31 = site is solid
     const uint8_t *rowdirty;  // per row (y, z): 1 if any site of the row has a bit set in nbmask
     float *rho_out;           // optional macros output (N floats) or nullptr
     float *u_out;             // optional macros output (3N floats) or nullptr
     double *partials;         // out: 4 doubles per workgroup
+};
+
+// One lattice of a batch.  The step arguments of domain d are s, with the
+// source and destination taken from buf[parity] and buf[parity ^ 1].
+struct DomDesc {
+    StepArgs s;               // src, dst, rho_out, u_out and partials unused
+    void *buf[2];             // the domain's two population arrays
+    int tile_begin;           // first tile of the domain in the batch's tile list
+    int ntiles;               // tiles of the domain
+    double n_fluid;           // fluid sites of the domain
+};
+
+// A step of a batch: every tile of every domain in one launch.
+struct BatchArgs {
+    const DomDesc *doms;      // device table, one entry per domain
+    const int *tile_dom;      // per tile: its domain
+    int ntiles;               // tiles of all domains
+    int parity;               // source arrays are buf[parity]
+    int tile_order;           // as in StepArgs
+    double *partials;         // out: 4 doubles per tile
+};
+
+// Per-domain totals of one batch step: domain d sums the partials of its
+// tiles (in order) into ring[d][step % kRingCap].
+struct BatchTotalsArgs {
+    const DomDesc *doms;
+    int ndoms;
+    const double *partials;   // 4 doubles per tile
+    unsigned int *ticket;     // arrival counter, 0 between launches
+    double *ring;             // ndoms x kRingCap x 4 doubles
+    unsigned long long *step_counter;
 };
 
 // The reduction of one step's partials into the ring of per-step totals.
@@ -94,7 +130,7 @@ struct TotalsArgs {
 struct InitArgs {
     void *dst;
     Layout lay;
-    int n;                    // N
+    int n;                    // N (sites, x fastest; inputs are unpadded)
     const double *rho;        // N or nullptr
     const double *u;          // 3N or nullptr
     const uint8_t *flags;     // device flags or nullptr
@@ -117,11 +153,32 @@ hipError_t launch_step(int codec, int variant, bool solids, bool macros, const S
 hipError_t launch_totals(const TotalsArgs &a, hipStream_t s);
 hipError_t launch_init(int codec, const InitArgs &a, hipStream_t s);
 hipError_t launch_macros(int codec, const MacroArgs &a, hipStream_t s);
-hipError_t launch_masks(const uint8_t *flags, int nx, int ny, int nz, uint32_t *nbmask, uint8_t *rowdirty,
+// Neighbour masks of a (nx, ny, nz) lattice stored with row pitch >= nx
+// (mask of site (x, row) at row * pitch + x); rowdirty per row.
+hipError_t launch_masks(const uint8_t *flags, int nx, int ny, int nz, int pitch, uint32_t *nbmask, uint8_t *rowdirty,
                         hipStream_t s);
 hipError_t launch_zero_solid_macros(const uint8_t *flags, int n, float *rho, float *u, hipStream_t s);
 hipError_t launch_copy(const void *src, void *dst, uint64_t bytes, hipStream_t s);
 int step_occupancy(int codec, int variant, bool solids, bool macros);  // workgroups per CU
+
+// Host helpers of the runtime files.  fail() records the message that
+// lb_last_error returns and passes the status code through.
+int fail(int code, const char *fmt, ...);
+long env_long(const char *name, long dflt);  // integer environment setting (tuning knobs)
+
+#define HIP_OR_FAIL(expr)                                                                         \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess) return lbm::fail(LB_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+// Batches: variant 1 / 2 / 3 as above (always with bounce-back masks).
+hipError_t launch_batch_step(int codec, int variant, const BatchArgs &a, int grid, hipStream_t s);
+hipError_t launch_batch_totals(const BatchTotalsArgs &a, hipStream_t s);
+int batch_occupancy(int codec, int variant);
+// Raw planes (19 x n elements of esize bytes, site order) to the storage
+// layout (to_state) or back.  Both pointers are device pointers.
+hipError_t launch_repack(void *planes, void *state, const Layout &lay, int64_t n, int esize, bool to_state,
+                         hipStream_t s);
 int sites_per_thread(int codec, int variant);
 
 }  // namespace lbm

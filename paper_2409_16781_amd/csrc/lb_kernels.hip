@@ -346,12 +346,12 @@ __device__ __forceinline__ void moments_of_totals(const float (&t)[kQ], float &m
 
 // ------------------------------------------------- FP64 totals per launch --
 // Each workgroup of a step reduces its threads' FP64 totals (through LDS in a
-// fixed tree) and stores them in partials[blockIdx.x]; no fence
+// fixed tree) and stores them in its slot of the partials; no fence
 // or atomic is needed there, because the totals are reduced by a second,
 // stream-ordered kernel (reduce_totals).  Every addition happens in a fixed
 // order, so the totals are bitwise reproducible.
 
-__device__ __forceinline__ void store_block_totals(const double (&acc)[4], double *partials)
+__device__ __forceinline__ void store_block_totals(const double (&acc)[4], double *out)
 {
     __shared__ double red[4][kBlock];
 #pragma unroll
@@ -367,7 +367,7 @@ __device__ __forceinline__ void store_block_totals(const double (&acc)[4], doubl
         }
         if (threadIdx.x == 0) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) partials[4 * blockIdx.x + k] = v[k];
+            for (int k = 0; k < 4; ++k) out[k] = v[k];
         }
     }
 }
@@ -538,214 +538,312 @@ constexpr int vec_waves()
 #endif
 }
 
-// NW: dwords per lane and population (16-, 8- or 4-byte accesses).
-template <int C, int NW, bool kSolids, bool kMacros>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(vec_waves<C, NW>()))) void step_vec(StepArgs a)
+// Workgroups are dispatched round-robin over the chip's 8 XCDs (workgroup b
+// runs on XCD b mod 8).  Order 1 gives each XCD a contiguous range of tiles:
+// a bijection of [0, ntiles) that leaves the last ntiles mod 8 tiles in place.
+__device__ __forceinline__ int tile_of(int b, int ntiles, int order)
+{
+    constexpr int kXcds = 8;
+    const int q = ntiles / kXcds;
+    if (order == 0 || b >= q * kXcds) return b;
+    return (b % kXcds) * q + b / kXcds;
+}
+
+// LDS of one workgroup for the x-edge exchange: the last (first) dword of
+// each row and wave, for the five c_x = +1 (-1) directions.
+struct EdgeLds {
+    uint32_t row_last[kBlock][5], row_first[kBlock][5];
+    uint32_t wave_last[kBlock / 64][5], wave_first[kBlock / 64][5];
+};
+
+// One tile (kBlock lanes, V sites each) of lattice a: gather with periodic
+// wrap and bounce-back, collide, store into dst, and add the FP64 totals of
+// the tile's fluid sites to acc.  NW: dwords per lane and population (16-,
+// 8- or 4-byte accesses).  kPadded: rows are stored with pitch > nx (a whole
+// number of vectors); the sites x >= nx of a row are held at zero like solid
+// sites and take no part in the totals.
+template <int C, int NW, bool kSolids, bool kMacros, bool kPadded>
+__device__ __forceinline__ void tile_update(const StepArgs &a, const char *src, char *dst, int tile,
+                                            double (&acc)[4], EdgeLds &lds)
 {
     using K = Codec<C>;
     constexpr int V = NW * 4 / K::kBytes;  // sites per lane
+    static_assert(!(kPadded && kMacros), "same-pass macros are written for unpadded rows");
     const Coll &cp = a.coll;
     const uint32_t nx = (uint32_t)a.nx, ny = (uint32_t)a.ny, nz = (uint32_t)a.nz;
-    const char *src = reinterpret_cast<const char *>(a.src);
-    char *dst = reinterpret_cast<char *>(a.dst);
+    const uint32_t pitch = kPadded ? a.lay.pitch : nx;
     const int lane = threadIdx.x & 63;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    const int ntiles = (a.nslots + kBlock - 1) / kBlock;
-    // x-edge elements exchanged between lanes of a tile: the last (first)
-    // dword of each row and wave, for the five c_x = +1 (-1) directions
-    __shared__ uint32_t edge_row_last[kBlock][5], edge_row_first[kBlock][5];
-    __shared__ uint32_t edge_wave_last[kBlock / 64][5], edge_wave_first[kBlock / 64][5];
 
-    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const int slot = tile * kBlock + (int)threadIdx.x;
-        const bool active = slot < a.nslots;
-        const uint32_t s0 = (uint32_t)(active ? slot : a.nslots - 1) * V;
-        const uint32_t row = fastdiv(s0, a.div_nx);
-        const uint32_t x0 = s0 - row * nx;
-        const uint32_t z = fastdiv(row, a.div_ny);
-        const uint32_t y = row - z * ny;
-        const uint32_t ym = (y == 0 ? ny : y) - 1, yp = (y + 1 == ny) ? 0 : y + 1;
-        const uint32_t zm = (z == 0 ? nz : z) - 1, zp = (z + 1 == nz) ? 0 : z + 1;
+    const int slot = tile * kBlock + (int)threadIdx.x;
+    const bool active = slot < a.nslots;
+    const uint32_t s0 = (uint32_t)(active ? slot : a.nslots - 1) * V;  // stored index of the first site
+    const uint32_t row = fastdiv(s0, a.div_pitch);
+    const uint32_t x0 = s0 - row * pitch;
+    const uint32_t z = fastdiv(row, a.div_ny);
+    const uint32_t y = row - z * ny;
+    const uint32_t ym = (y == 0 ? ny : y) - 1, yp = (y + 1 == ny) ? 0 : y + 1;
+    const uint32_t zm = (z == 0 ? nz : z) - 1, zp = (z + 1 == nz) ? 0 : z + 1;
 
-        // start (element offset) of the pulled source row of each population
-        uint64_t rb[kQ];
+    // start (element offset) of the pulled source row of each population
+    uint64_t rb[kQ];
 #pragma unroll
-        for (int i = 0; i < kQ; ++i) {
-            const uint32_t ys = CY[i] > 0 ? ym : (CY[i] < 0 ? yp : y);
-            const uint32_t zs = CZ[i] > 0 ? zm : (CZ[i] < 0 ? zp : z);
-            rb[i] = a.lay.row_base(zs * ny + ys) + (uint64_t)i * a.lay.seg;
-        }
-        const uint64_t own = a.lay.row_base(row) + x0;  // this lane's first site, population 0
+    for (int i = 0; i < kQ; ++i) {
+        const uint32_t ys = CY[i] > 0 ? ym : (CY[i] < 0 ? yp : y);
+        const uint32_t zs = CZ[i] > 0 ? zm : (CZ[i] < 0 ? zp : z);
+        rb[i] = a.lay.row_base(zs * ny + ys) + (uint64_t)i * a.lay.seg;
+    }
+    const uint64_t own = a.lay.row_base(row) + x0;  // this lane's first site, population 0
 
-        Lane<NW> d[kQ];
+    Lane<NW> d[kQ];
 #pragma unroll
-        for (int i = 0; i < kQ; ++i) d[i] = ldv<NW>(src + (rb[i] + x0) * K::kBytes);
+    for (int i = 0; i < kQ; ++i) d[i] = ldv<NW>(src + (rb[i] + x0) * K::kBytes);
 
-        // +-1 shifts along x (all lanes take part in the DPP moves).  The
-        // element a lane needs from beyond its wave or across the periodic
-        // wrap comes through LDS when the tile holds whole rows (each
-        // element is then read from HBM once), else by a direct load.
-        const bool left_edge = (lane == 0) || (x0 == 0);
-        const bool right_edge = (lane == 63) || (x0 + V == nx);
-        const int wave = threadIdx.x >> 6;
-        const int rit = (int)threadIdx.x >> a.lg_row_lanes;  // row within the tile
-        if (a.lds_edges) {
-            __syncthreads();  // the previous tile's readers are done
-            if (x0 + V == nx) {
+    // +-1 shifts along x (all lanes take part in the DPP moves).  The element
+    // a lane needs from beyond its wave or across the periodic wrap comes
+    // through LDS when the tile holds whole rows (each element is then read
+    // from HBM once), else by a direct load.  The lane holding site nx - 1
+    // is the row's right edge (with padded rows that site need not be the
+    // last of the vector).
+    const bool left_edge = (lane == 0) || (x0 == 0);
+    const bool row_end = x0 + V >= nx;
+    const bool right_edge = (lane == 63) || row_end;
+    const int wave = threadIdx.x >> 6;
+    const int rit = (int)threadIdx.x >> a.lg_row_lanes;  // row within the tile
+    if (a.lds_edges) {
+        __syncthreads();  // the previous tile's readers are done
+        if (row_end) {
 #pragma unroll
-                for (int k = 0; k < 5; ++k) edge_row_last[rit][k] = d[kPlusX[k]].w[NW - 1];
-            }
-            if (x0 == 0) {
-#pragma unroll
-                for (int k = 0; k < 5; ++k) edge_row_first[rit][k] = d[kMinusX[k]].w[0];
-            }
-            if (lane == 63) {
-#pragma unroll
-                for (int k = 0; k < 5; ++k) edge_wave_last[wave][k] = d[kPlusX[k]].w[NW - 1];
-            }
-            if (lane == 0) {
-#pragma unroll
-                for (int k = 0; k < 5; ++k) edge_wave_first[wave][k] = d[kMinusX[k]].w[0];
-            }
-            __syncthreads();
+            for (int k = 0; k < 5; ++k) lds.row_last[rit][k] = d[kPlusX[k]].w[NW - 1];
         }
-        const uint32_t xl = (x0 == 0 ? nx : x0) - 1;
-        const uint32_t xr = (x0 + V == nx) ? 0 : x0 + V;
+        if (x0 == 0) {
 #pragma unroll
-        for (int k = 0; k < 5; ++k) {
-            const int i = kPlusX[k];  // c_x = +1: pull from x - 1
-            uint32_t prev = wave_shr1(d[i].w[NW - 1]);
-            if (left_edge) {
-                if (a.lds_edges) {
-                    prev = x0 == 0 ? edge_row_last[rit][k] : edge_wave_last[wave - 1][k];
-                } else {
-                    prev = ld_elem<C>(src, rb[i] + xl);
-                    if constexpr (K::kBytes == 2) prev <<= 16;  // as the upper half of a dword
-                }
-            }
-            if constexpr (K::kBytes == 2) prev >>= 16;
-            d[i] = shift_in_from_left<C, NW>(d[i], prev);
+            for (int k = 0; k < 5; ++k) lds.row_first[rit][k] = d[kMinusX[k]].w[0];
         }
+        if (lane == 63) {
 #pragma unroll
-        for (int k = 0; k < 5; ++k) {
-            const int i = kMinusX[k];  // c_x = -1: pull from x + 1
-            uint32_t next = wave_shl1(d[i].w[0]);
-            if (right_edge) {
-                if (a.lds_edges)
-                    next = x0 + V == nx ? edge_row_first[rit][k] : edge_wave_first[wave + 1][k];
-                else
-                    next = ld_elem<C>(src, rb[i] + xr);
-            }
-            if constexpr (K::kBytes == 2) next &= 0xffffu;
-            d[i] = shift_in_from_right<C, NW>(d[i], next);
+            for (int k = 0; k < 5; ++k) lds.wave_last[wave][k] = d[kPlusX[k]].w[NW - 1];
         }
-
-        // halfway bounce-back: where x - c_i is solid, take the site's own opp(i) value
-        uint32_t own_solid = 0;  // bit e: site e of this lane is solid
-        if constexpr (kSolids) {
-            if (a.rowdirty[row]) {
-                uint32_t m[V];
-                load_masks<V>(a.nbmask + s0, m);
+        if (lane == 0) {
 #pragma unroll
-                for (int e = 0; e < V; ++e) own_solid |= (m[e] >> 31) << e;
-#pragma unroll
-                for (int i = 1; i < kQ; ++i) {
-                    uint32_t sel = 0;  // bit e set: element e bounces back
-#pragma unroll
-                    for (int e = 0; e < V; ++e) sel |= ((m[e] >> i) & 1u) << e;
-                    if (sel) {
-                        const Lane<NW> o = ldv<NW>(src + (own + OPP[i] * a.lay.seg) * K::kBytes);
-#pragma unroll
-                        for (int e = 0; e < V; ++e)
-                            if ((sel >> e) & 1u) vset<C, NW>(d[i], e, vget<C, NW>(o, e));
-                    }
-                }
-            }
+            for (int k = 0; k < 5; ++k) lds.wave_first[wave][k] = d[kMinusX[k]].w[0];
         }
-
-        // collide site by site (16-bit codecs: two sites per dword at a time)
-        float mr[V], mu[V], mv[V], mw[V];
-        if constexpr (K::kBytes == 4) {
+        __syncthreads();
+    }
+    const uint32_t xl = (x0 == 0 ? nx : x0) - 1;
+    const uint32_t xr = row_end ? 0 : x0 + V;
 #pragma unroll
-            for (int e = 0; e < V; ++e) {
-                float g[kQ];
-#pragma unroll
-                for (int i = 0; i < kQ; ++i) g[i] = K::dec(d[i].w[e]);
-                collide(g, cp, mr[e], mu[e], mv[e], mw[e]);
-#pragma unroll
-                for (int i = 0; i < kQ; ++i) d[i].w[e] = K::enc(g[i]);
-            }
-        } else {
-#pragma unroll
-            for (int j = 0; j < NW; ++j) {
-                float g0[kQ], g1[kQ];
-#pragma unroll
-                for (int i = 0; i < kQ; ++i) K::dec2(d[i].w[j], g0[i], g1[i]);
-                collide(g0, cp, mr[2 * j], mu[2 * j], mv[2 * j], mw[2 * j]);
-                collide(g1, cp, mr[2 * j + 1], mu[2 * j + 1], mv[2 * j + 1], mw[2 * j + 1]);
-#pragma unroll
-                for (int i = 0; i < kQ; ++i) d[i].w[j] = K::enc2(g0[i], g1[i]);
-            }
-        }
-        if constexpr (kSolids || kMacros) {
-#pragma unroll
-            for (int e = 0; e < V; ++e) {
-                if ((own_solid >> e) & 1u) mr[e] = mu[e] = mv[e] = mw[e] = 0.0f;
-            }
-        }
-
-        if (active) {
-            if (own_solid == 0) {
-#pragma unroll
-                for (int i = 0; i < kQ; ++i) stv<NW>(dst + (own + i * a.lay.seg) * K::kBytes, d[i]);
-            } else if (own_solid != (1u << V) - 1u) {
-#pragma unroll
-                for (int i = 0; i < kQ; ++i)
-#pragma unroll
-                    for (int e = 0; e < V; ++e)
-                        if (!((own_solid >> e) & 1u)) st_elem<C>(dst, own + i * a.lay.seg + e, vget<C, NW>(d[i], e));
-            }
-            if constexpr (kMacros) {
-                const size_t n = (size_t)nx * ny * nz;
-                store_floats<V>(a.rho_out + s0, mr);
-                store_floats<V>(a.u_out + s0, mu);
-                store_floats<V>(a.u_out + n + s0, mv);
-                store_floats<V>(a.u_out + 2 * n + s0, mw);
-            }
-            // totals of the values as stored (after rounding), fluid sites only
-            float tot[kQ];
-            if (own_solid == 0) {
-#pragma unroll
-                for (int i = 0; i < kQ; ++i) {
-                    float t = 0.0f;
-#pragma unroll
-                    for (int j = 0; j < NW; ++j) {
-                        if constexpr (K::kBytes == 4)
-                            t += K::dec(d[i].w[j]);
-                        else
-                            t = K::sum2(d[i].w[j], t);
-                    }
-                    tot[i] = t;
-                }
+    for (int k = 0; k < 5; ++k) {
+        const int i = kPlusX[k];  // c_x = +1: pull from x - 1
+        uint32_t prev = wave_shr1(d[i].w[NW - 1]);
+        if (left_edge) {
+            if (a.lds_edges) {
+                prev = x0 == 0 ? lds.row_last[rit][k] : lds.wave_last[wave - 1][k];
             } else {
-#pragma unroll
-                for (int i = 0; i < kQ; ++i) {
-                    float t = 0.0f;
-#pragma unroll
-                    for (int e = 0; e < V; ++e)
-                        if (!((own_solid >> e) & 1u)) t += K::dec(vget<C, NW>(d[i], e));
-                    tot[i] = t;
-                }
+                prev = ld_elem<C>(src, rb[i] + xl);
+                if constexpr (K::kBytes == 2) prev <<= 16;  // as the upper half of a dword
             }
-            float m, px, py, pz;
-            moments_of_totals(tot, m, px, py, pz);
-            acc[0] += (double)m;
-            acc[1] += (double)px;
-            acc[2] += (double)py;
-            acc[3] += (double)pz;
+        }
+        if constexpr (K::kBytes == 2) prev >>= 16;
+        d[i] = shift_in_from_left<C, NW>(d[i], prev);
+    }
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const int i = kMinusX[k];  // c_x = -1: pull from x + 1
+        uint32_t next = wave_shl1(d[i].w[0]);
+        if (right_edge) {
+            if (a.lds_edges)
+                next = row_end ? lds.row_first[rit][k] : lds.wave_first[wave + 1][k];
+            else
+                next = ld_elem<C>(src, rb[i] + xr);
+        }
+        if constexpr (K::kBytes == 2) next &= 0xffffu;
+        d[i] = shift_in_from_right<C, NW>(d[i], next);
+        if constexpr (kPadded) {
+            // site nx - 1 inside the vector: it pulls x = 0 of the row
+            if (x0 + V > nx) {
+#pragma unroll
+                for (int e = 0; e < V - 1; ++e)
+                    if (x0 + e + 1 == nx) vset<C, NW>(d[i], e, next);
+            }
         }
     }
-    store_block_totals(acc, a.partials);
+
+    // halfway bounce-back: where x - c_i is solid, take the site's own opp(i)
+    // value.  dead: bit e set if site e of this lane is solid (or padding).
+    uint32_t dead = 0;
+    if constexpr (kPadded) {
+#pragma unroll
+        for (int e = 1; e < V; ++e) dead |= (x0 + e >= nx ? 1u : 0u) << e;
+    }
+    if constexpr (kSolids) {
+        if (a.rowdirty[row]) {
+            uint32_t m[V];
+            load_masks<V>(a.nbmask + s0, m);
+#pragma unroll
+            for (int e = 0; e < V; ++e) dead |= (m[e] >> 31) << e;
+#pragma unroll
+            for (int i = 1; i < kQ; ++i) {
+                uint32_t sel = 0;  // bit e set: element e bounces back
+#pragma unroll
+                for (int e = 0; e < V; ++e) sel |= ((m[e] >> i) & 1u) << e;
+                if (sel) {
+                    const Lane<NW> o = ldv<NW>(src + (own + OPP[i] * a.lay.seg) * K::kBytes);
+#pragma unroll
+                    for (int e = 0; e < V; ++e)
+                        if ((sel >> e) & 1u) vset<C, NW>(d[i], e, vget<C, NW>(o, e));
+                }
+            }
+        }
+    }
+
+    // collide site by site (16-bit codecs: two sites per dword at a time)
+    float mr[V], mu[V], mv[V], mw[V];
+    if constexpr (K::kBytes == 4) {
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            float g[kQ];
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) g[i] = K::dec(d[i].w[e]);
+            collide(g, cp, mr[e], mu[e], mv[e], mw[e]);
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) d[i].w[e] = K::enc(g[i]);
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < NW; ++j) {
+            float g0[kQ], g1[kQ];
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) K::dec2(d[i].w[j], g0[i], g1[i]);
+            collide(g0, cp, mr[2 * j], mu[2 * j], mv[2 * j], mw[2 * j]);
+            collide(g1, cp, mr[2 * j + 1], mu[2 * j + 1], mv[2 * j + 1], mw[2 * j + 1]);
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) d[i].w[j] = K::enc2(g0[i], g1[i]);
+        }
+    }
+
+    if (active) {
+        // Solid (and padding) sites hold zero in both arrays: they are
+        // written as zero inside a vector with fluid sites (whole-vector
+        // stores) and not at all in an all-solid vector.  The zeros add
+        // nothing to the totals below.
+        if constexpr (kSolids || kPadded) {
+            if (dead) {
+#pragma unroll
+                for (int e = 0; e < V; ++e) {
+                    if ((dead >> e) & 1u) {
+                        mr[e] = mu[e] = mv[e] = mw[e] = 0.0f;
+#pragma unroll
+                        for (int i = 0; i < kQ; ++i) vset<C, NW>(d[i], e, 0u);
+                    }
+                }
+            }
+        }
+        if (dead != (1u << V) - 1u) {
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) stv<NW>(dst + (own + i * a.lay.seg) * K::kBytes, d[i]);
+        }
+        if constexpr (kMacros) {
+            const size_t n = (size_t)nx * ny * nz;
+            store_floats<V>(a.rho_out + s0, mr);
+            store_floats<V>(a.u_out + s0, mu);
+            store_floats<V>(a.u_out + n + s0, mv);
+            store_floats<V>(a.u_out + 2 * n + s0, mw);
+        }
+        // totals of the values as stored (after rounding), fluid sites only
+        float tot[kQ];
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) {
+            float t = 0.0f;
+#pragma unroll
+            for (int j = 0; j < NW; ++j) {
+                if constexpr (K::kBytes == 4)
+                    t += K::dec(d[i].w[j]);
+                else
+                    t = K::sum2(d[i].w[j], t);
+            }
+            tot[i] = t;
+        }
+        float m, px, py, pz;
+        moments_of_totals(tot, m, px, py, pz);
+        acc[0] += (double)m;
+        acc[1] += (double)px;
+        acc[2] += (double)py;
+        acc[3] += (double)pz;
+    }
+}
+
+// One step of one lattice: one workgroup per tile (or a capped grid looping
+// over tiles); each workgroup stores the FP64 totals of its tiles.
+template <int C, int NW, bool kSolids, bool kMacros>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(vec_waves<C, NW>()))) void step_vec(StepArgs a)
+{
+    __shared__ EdgeLds lds;
+    const char *src = reinterpret_cast<const char *>(a.src);
+    char *dst = reinterpret_cast<char *>(a.dst);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const int ntiles = (a.nslots + kBlock - 1) / kBlock;
+    for (int b = blockIdx.x; b < ntiles; b += gridDim.x)
+        tile_update<C, NW, kSolids, kMacros, false>(a, src, dst, tile_of(b, ntiles, a.tile_order), acc, lds);
+    store_block_totals(acc, a.partials + 4 * (size_t)blockIdx.x);
+}
+
+// One step of a batch of lattices: the tiles of all domains in one launch.
+// The domain table is read through the constant address space, so the
+// per-tile domain parameters (uniform per workgroup) come in with scalar
+// loads and live in scalar registers.
+// Address space 4 exists only in the device pass (the host pass parses the
+// kernel bodies but generates no code for them).
+#if defined(__HIP_DEVICE_COMPILE__)
+#define LB_CONSTANT_AS __attribute__((address_space(4)))
+#else
+#define LB_CONSTANT_AS
+#endif
+typedef LB_CONSTANT_AS const DomDesc ConstDomDesc;
+typedef LB_CONSTANT_AS const int ConstInt;
+
+template <int C, int NW>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(vec_waves<C, NW>()))) void step_batch(BatchArgs a)
+{
+    __shared__ EdgeLds lds;
+    for (int b = blockIdx.x; b < a.ntiles; b += gridDim.x) {
+        const int t = tile_of(b, a.ntiles, a.tile_order);
+        const int dom = ((ConstInt *)a.tile_dom)[t];
+        ConstDomDesc &D = ((ConstDomDesc *)a.doms)[dom];
+        const StepArgs s = D.s;
+        const char *src = reinterpret_cast<const char *>(D.buf[a.parity]);
+        char *dst = reinterpret_cast<char *>(D.buf[a.parity ^ 1]);
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        tile_update<C, NW, true, false, true>(s, src, dst, t - D.tile_begin, acc, lds);
+        store_block_totals(acc, a.partials + 4 * (size_t)t);
+        __syncthreads();  // the totals' LDS is reused by the next tile
+    }
+}
+
+// Per-domain totals of a batch step: workgroup d sums the partials of domain
+// d's tiles in order and stores {mass, momentum} in the domain's ring; the
+// last workgroup to finish advances the step counter.
+__global__ __launch_bounds__(kBlock) void reduce_domains(BatchTotalsArgs a)
+{
+    __shared__ int is_last;
+    const int d = blockIdx.x;
+    const unsigned long long step = __hip_atomic_load(a.step_counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    double tot[4];
+    block_sum4(a.partials + 4 * (size_t)a.doms[d].tile_begin, a.doms[d].ntiles, tot, false);
+    if (threadIdx.x == 0) {
+        double *r = a.ring + 4 * ((size_t)d * kRingCap + step % kRingCap);
+        r[0] = a.doms[d].n_fluid + tot[0];
+        r[1] = tot[1];
+        r[2] = tot[2];
+        r[3] = tot[3];
+        __threadfence();
+        const unsigned int prev = atomicAdd(a.ticket, 1u);
+        is_last = (prev == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (is_last && threadIdx.x == 0) {
+        __hip_atomic_store(a.step_counter, step + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(a.ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
 // ---------------------------------------------- step: one site per thread --
@@ -767,7 +865,7 @@ __global__ __launch_bounds__(kBlock) void step_site(StepArgs a)
         const int slot = tile * kBlock + (int)threadIdx.x;
         if (slot >= a.nslots) continue;
         const uint32_t s = (uint32_t)slot;
-        const uint32_t row = fastdiv(s, a.div_nx);
+        const uint32_t row = fastdiv(s, a.div_pitch);
         const uint32_t x = s - row * nx;
         const uint32_t z = fastdiv(row, a.div_ny);
         const uint32_t y = row - z * ny;
@@ -816,7 +914,7 @@ __global__ __launch_bounds__(kBlock) void step_site(StepArgs a)
         acc[2] += (double)py;
         acc[3] += (double)pz;
     }
-    store_block_totals(acc, a.partials);
+    store_block_totals(acc, a.partials + 4 * (size_t)blockIdx.x);
 }
 
 // Solid sites get zero macros in the one-site kernel (it skips them).
@@ -895,31 +993,59 @@ __global__ __launch_bounds__(kBlock) void macros_kernel(MacroArgs a)
 
 // ------------------------------------------------------ neighbour masks --
 // bit i (1..18): site x - c_i is solid; bit 31: the site itself is solid.
+// Masks are stored like the populations' rows, with pitch >= nx (the padding
+// sites of a row get mask 0).
 
-__global__ __launch_bounds__(kBlock) void build_masks(const uint8_t *flags, int nx, int ny, int nz, uint32_t *nbmask)
+__global__ __launch_bounds__(kBlock) void build_masks(const uint8_t *flags, int nx, int ny, int nz, int pitch,
+                                                      uint32_t *nbmask)
 {
-    const int n = nx * ny * nz;
+    const int64_t n = (int64_t)pitch * ny * nz;
     for (int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x; s < n; s += (int64_t)gridDim.x * kBlock) {
-        const int x = s % nx, y = (s / nx) % ny, z = s / (nx * ny);
-        uint32_t m = flags[s] ? (1u << 31) : 0u;
+        const int x = (int)(s % pitch);
+        const int64_t row = s / pitch;
+        const int y = (int)(row % ny), z = (int)(row / ny);
+        uint32_t m = 0;
+        if (x < nx) {
+            m = flags[row * nx + x] ? (1u << 31) : 0u;
 #pragma unroll
-        for (int i = 1; i < kQ; ++i) {
-            int xs = x - CX[i], ys = y - CY[i], zs = z - CZ[i];
-            xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
-            ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
-            zs = zs < 0 ? zs + nz : (zs >= nz ? zs - nz : zs);
-            if (flags[(zs * ny + ys) * nx + xs]) m |= 1u << i;
+            for (int i = 1; i < kQ; ++i) {
+                int xs = x - CX[i], ys = y - CY[i], zs = z - CZ[i];
+                xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
+                ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
+                zs = zs < 0 ? zs + nz : (zs >= nz ? zs - nz : zs);
+                if (flags[((int64_t)zs * ny + ys) * nx + xs]) m |= 1u << i;
+            }
         }
         nbmask[s] = m;
     }
 }
 
-__global__ __launch_bounds__(kBlock) void build_rowdirty(const uint32_t *nbmask, int nx, int nrows, uint8_t *rowdirty)
+__global__ __launch_bounds__(kBlock) void build_rowdirty(const uint32_t *nbmask, int pitch, int nrows, uint8_t *rowdirty)
 {
     for (int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x; r < nrows; r += (int64_t)gridDim.x * kBlock) {
         uint32_t any = 0;
-        for (int x = 0; x < nx; ++x) any |= nbmask[(size_t)r * nx + x];
+        for (int x = 0; x < pitch; ++x) any |= nbmask[(size_t)r * pitch + x];
         rowdirty[r] = any ? 1 : 0;
+    }
+}
+
+// ------------------------------------------------------------- raw state --
+// Between raw population planes (19 x N elements, plane i holds population i
+// of every site in site order) and the storage layout.
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void repack_kernel(T *planes, T *state, Layout lay, int64_t n, int to_state)
+{
+    const int64_t total = (int64_t)kQ * n;
+    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < total; k += (int64_t)gridDim.x * kBlock) {
+        const int i = (int)(k / n);
+        const int64_t s = k - (int64_t)i * n;
+        const uint32_t row = (uint32_t)(s / lay.nx);
+        const uint64_t li = lay.row_base(row) + (uint64_t)i * lay.seg + (uint64_t)(s - (int64_t)row * lay.nx);
+        if (to_state)
+            state[li] = planes[k];
+        else
+            planes[k] = state[li];
     }
 }
 
@@ -1014,6 +1140,58 @@ hipError_t launch_step(int codec, int variant, bool solids, bool macros, const S
     return hipLaunchKernel(fn, dim3(grid), dim3(kBlock), params, 0, s);
 }
 
+namespace {
+template <int C>
+void *batch_fn(int variant)
+{
+    if (variant == 1) return reinterpret_cast<void *>(&step_batch<C, 4>);
+    if (variant == 2) return reinterpret_cast<void *>(&step_batch<C, 2>);
+    return reinterpret_cast<void *>(&step_batch<C, 1>);
+}
+
+void *pick_batch(int codec, int variant)
+{
+    switch (codec) {
+        case kF32: return batch_fn<kF32>(variant);
+        case kF16: return batch_fn<kF16>(variant);
+        default: return batch_fn<kBF16>(variant);
+    }
+}
+}  // namespace
+
+hipError_t launch_batch_step(int codec, int variant, const BatchArgs &a, int grid, hipStream_t s)
+{
+    BatchArgs arg = a;
+    void *params[] = {&arg};
+    return hipLaunchKernel(pick_batch(codec, variant), dim3(grid), dim3(kBlock), params, 0, s);
+}
+
+hipError_t launch_repack(void *planes, void *state, const Layout &lay, int64_t n, int esize, bool to_state,
+                         hipStream_t s)
+{
+    const int g = grid_for((uint64_t)kQ * n);
+    if (esize == 4)
+        repack_kernel<uint32_t><<<g, kBlock, 0, s>>>(static_cast<uint32_t *>(planes), static_cast<uint32_t *>(state),
+                                                     lay, n, to_state ? 1 : 0);
+    else
+        repack_kernel<uint16_t><<<g, kBlock, 0, s>>>(static_cast<uint16_t *>(planes), static_cast<uint16_t *>(state),
+                                                     lay, n, to_state ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_totals(const BatchTotalsArgs &a, hipStream_t s)
+{
+    reduce_domains<<<a.ndoms, kBlock, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+int batch_occupancy(int codec, int variant)
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pick_batch(codec, variant), kBlock, 0) != hipSuccess) return 1;
+    return nb < 1 ? 1 : nb;
+}
+
 hipError_t launch_totals(const TotalsArgs &a, hipStream_t s)
 {
     const int g = (a.nparts + kRedChunk - 1) / kRedChunk;
@@ -1043,12 +1221,11 @@ hipError_t launch_macros(int codec, const MacroArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_masks(const uint8_t *flags, int nx, int ny, int nz, uint32_t *nbmask, uint8_t *rowdirty,
+hipError_t launch_masks(const uint8_t *flags, int nx, int ny, int nz, int pitch, uint32_t *nbmask, uint8_t *rowdirty,
                         hipStream_t s)
 {
-    const int n = nx * ny * nz;
-    build_masks<<<grid_for((uint64_t)n), kBlock, 0, s>>>(flags, nx, ny, nz, nbmask);
-    build_rowdirty<<<grid_for((uint64_t)ny * nz), kBlock, 0, s>>>(nbmask, nx, ny * nz, rowdirty);
+    build_masks<<<grid_for((uint64_t)pitch * ny * nz), kBlock, 0, s>>>(flags, nx, ny, nz, pitch, nbmask);
+    build_rowdirty<<<grid_for((uint64_t)ny * nz), kBlock, 0, s>>>(nbmask, pitch, ny * nz, rowdirty);
     return hipGetLastError();
 }
 

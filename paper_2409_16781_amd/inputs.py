@@ -16,6 +16,8 @@ Workloads (all lattice units):
   walls, the boundary type of the paper's lid-driven cavity, Section 3.3).
 * Porous channel: channel walls plus seeded random spheres to a target
   porosity.
+* Batch: many porous channels of seeded random extents and relaxation times
+  (``batch_domains``).
 * Noise: i.i.d. uniform in [-a, a], drawn once in float64 with
   ``numpy.random.default_rng(seed)`` in C order (component, z, y, x).
 """
@@ -71,20 +73,38 @@ def sphere_flags(nx: int, ny: int, nz: int, porosity: float, seed: int,
 
     Sphere centres are uniform over the box and radii uniform in [rmin, rmax];
     spheres are added until the fluid fraction drops to ``porosity`` or below.
+    A site belongs to a sphere when its periodic (minimum-image) distance to
+    the centre is at most the radius.  Each sphere is drawn only inside its
+    bounding box (the sites within reach of the centre along each axis).
     """
     rng = np.random.default_rng(seed)
     f = channel_flags(nx, ny, nz) if walls else np.zeros((nz, ny, nx), dtype=np.uint8)
-    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
     total = nx * ny * nz
+    solid = int(f.sum())
+
+    def reach(c, r, n):
+        # integer coordinates within distance r of c (periodic), as int64
+        lo, hi = int(np.floor(c - r)), int(np.ceil(c + r))
+        if hi - lo + 1 >= n:
+            return np.arange(n, dtype=np.int64)
+        return np.unique(np.arange(lo, hi + 1, dtype=np.int64) % n)
+
     for _ in range(100000):
-        if 1.0 - f.sum() / total <= porosity:
+        if 1.0 - solid / total <= porosity:
             break
         c = rng.uniform(0, 1, 3) * np.array([nx, ny, nz])
         r = rng.uniform(rmin, rmax)
-        dx = np.abs(x - c[0]); dx = np.minimum(dx, nx - dx)
-        dy = np.abs(y - c[1]); dy = np.minimum(dy, ny - dy)
-        dz = np.abs(z - c[2]); dz = np.minimum(dz, nz - dz)
-        f[(dx * dx + dy * dy + dz * dz) <= r * r] = 1
+        xs, ys, zs = reach(c[0], r, nx), reach(c[1], r, ny), reach(c[2], r, nz)
+        dx = np.abs(xs - c[0]); dx = np.minimum(dx, nx - dx)
+        dy = np.abs(ys - c[1]); dy = np.minimum(dy, ny - dy)
+        dz = np.abs(zs - c[2]); dz = np.minimum(dz, nz - dz)
+        inside = (dx[None, None, :] * dx[None, None, :] + dy[None, :, None] * dy[None, :, None]
+                  + dz[:, None, None] * dz[:, None, None]) <= r * r
+        box = np.ix_(zs, ys, xs)
+        sub = f[box]
+        solid += int(np.count_nonzero(inside & (sub == 0)))
+        sub[inside] = 1
+        f[box] = sub
     return f
 
 
@@ -122,6 +142,29 @@ def channel(nx: int = 256, ny: int = 128, nz: int = 128, tau: float = 0.6, g: fl
     u = np.zeros((3, nz, ny, nx))
     return dict(name=f"channel{nx}x{ny}x{nz}", shape=(nz, ny, nx), rho=rho, u=u,
                 flags=channel_flags(nx, ny, nz), tau=tau, force=(g, 0.0, 0.0), steps=steps)
+
+
+def batch_domains(count: int = 64, nmin: int = 16, nmax: int = 96, porosity: float = 0.8,
+                  tau_lo: float = 0.55, tau_hi: float = 1.0, g: float = 1e-6, noise: float = 1e-4, seed: int = 3):
+    """Batch of independent porous channel domains.
+
+    Extents nx, ny, nz drawn independently and uniformly from {nmin..nmax};
+    tau uniform in [tau_lo, tau_hi]; walls at y = 0 and ny-1 plus random
+    spheres of radius U[2, 6] to the given porosity (sphere seed
+    1000 * seed + d for domain d); force (g, 0, 0); rho = 1 + U(+-noise)
+    (seed 2000 * seed + d), u = 0.  Returns a list of per-domain dicts.
+    """
+    rng = np.random.default_rng(seed)
+    dims = rng.integers(nmin, nmax + 1, size=(count, 3))
+    taus = rng.uniform(tau_lo, tau_hi, size=count)
+    out = []
+    for d in range(count):
+        nx, ny, nz = (int(v) for v in dims[d])
+        flags = sphere_flags(nx, ny, nz, porosity, 1000 * seed + d, rmin=2.0, rmax=6.0, walls=True)
+        rho = 1.0 + uniform_noise((nz, ny, nx), noise, 2000 * seed + d)
+        out.append(dict(name=f"batch{d}", shape=(nz, ny, nx), rho=rho, u=np.zeros((3, nz, ny, nx)),
+                        flags=flags, tau=float(taus[d]), force=(g, 0.0, 0.0)))
+    return out
 
 
 def tgv_noise_box(n: int = 512, u0: float = 0.01, tau: float = 0.55, steps: int = 1000,

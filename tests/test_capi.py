@@ -82,3 +82,42 @@ def test_tau_infinity_is_accepted_by_validation():
         L.lb_destroy(h)
     else:
         assert "tau" not in lbm.last_error()
+
+
+def _batch_create(dims, taus, flags=None, storage=0):
+    L = lbm.lib()
+    d = np.ascontiguousarray(np.array(dims, dtype=np.int32).reshape(-1))
+    t = np.ascontiguousarray(np.array(taus, dtype=np.float64))
+    return L.lb_batch_create(len(taus), d.ctypes.data_as(ctypes.c_void_p), t.ctypes.data_as(ctypes.c_void_p),
+                             flags, storage, None, 0)
+
+
+@pytest.mark.parametrize("dims,taus,needle", [
+    ([(4, 4, 4), (0, 4, 4)], [0.8, 0.8], "extents"),
+    ([(4, 4, 4), (4, 4, 4)], [0.8, 0.5], "tau"),
+    ([(4, 4, 4)], [float("nan")], "tau"),
+    ([(1 << 11, 1 << 10, 1 << 10)], [0.8], "too large"),
+])
+def test_batch_create_rejects_bad_arguments(dims, taus, needle):
+    assert not _batch_create(dims, taus)
+    assert needle in lbm.last_error()
+
+
+def test_batch_create_rejects_bad_codec_and_count():
+    assert not _batch_create([(4, 4, 4)], [0.8], storage=9)
+    assert "codec" in lbm.last_error()
+    L = lbm.lib()
+    assert not L.lb_batch_create(0, None, None, None, 0, None, 0)
+    assert "count" in lbm.last_error()
+
+
+def test_batch_null_handle_is_rejected_everywhere():
+    L = lbm.lib()
+    assert L.lb_batch_step(None, 1) == lbm.LB_ESTATE
+    assert L.lb_batch_macros(None, 0, None, None) == lbm.LB_ESTATE
+    assert L.lb_batch_set_force(None, -1, 0.0, 0.0, 0.0) == lbm.LB_ESTATE
+    assert L.lb_batch_sums(None, 0, None, 1) == lbm.LB_ESTATE
+    assert L.lb_batch_sync(None) == lbm.LB_ESTATE
+    assert L.lb_batch_steps_done(None) == -1
+    assert L.lb_batch_query(None, 0) == -1
+    L.lb_batch_destroy(None)  # no-op
