@@ -8,7 +8,10 @@ imports nothing from it.
 The method it implements is the paper's Eq. 1-3 (Section 2, "Lattice Boltzmann
 Method") in the fused two-array form of Section 3.1, on the D3Q19 velocity set,
 with Guo forcing and halfway bounce-back; ``d3q19_oracle.c`` lists each step
-and each reading of the paper.
+and each reading of the paper.  It also holds the adjoint of one step (the
+transposed collision Jacobian and the transposed streaming) and a
+checkpointed gradient of the outlet mass flux with respect to a per-site
+x-force.
 
 Array conventions (all numpy, C-contiguous):
   state S   float64, shape (19, nz, ny, nx), unshifted populations
@@ -63,6 +66,9 @@ def _load():
         lib.oracle_run.restype = ci
         lib.oracle_macros.argtypes = [ci, ci, ci, u8, d, d, d, d, d]
         lib.oracle_sums.argtypes = [ci, ci, ci, u8, d, d]
+        lib.oracle_collision_jacobian.argtypes = [ctypes.c_double, d, d, d, d]
+        lib.oracle_adjoint_step.argtypes = [ci, ci, ci, u8, ctypes.c_double, d, d, d, d, d, d]
+        lib.oracle_adjoint_step.restype = ci
         _lib = lib
     return _lib
 
@@ -166,6 +172,77 @@ def sums(S, flags=None) -> np.ndarray:
     out = np.zeros(4)
     _load().oracle_sums(nx, ny, nz, _fp(flags, (nz, ny, nx)), _dp(S), _dp(out))
     return out
+
+
+def collision_jacobian(f, tau, F):
+    """(J[19, 19], dFx[19]): J[i, j] = dC_i/df_j and dC_i/dF_x of one site's
+    collision for pre-collision populations f and force density F."""
+    f = np.ascontiguousarray(f, dtype=np.float64).reshape(Q)
+    J = np.zeros((Q, Q))
+    dF = np.zeros(Q)
+    omega = 0.0 if np.isinf(tau) else 1.0 / tau
+    _load().oracle_collision_jacobian(omega, _dp(f), _dp(_vec3(F)), _dp(J), _dp(dF))
+    return J, dF
+
+
+def adjoint_step(S_n, lam_next, tau, F=None, flags=None, Fx_field=None):
+    """Adjoint of the step taken from S_n: returns (dJ/dS_n, dJ/dF_x increment)
+    given lam_next = dJ/dS_{n+1}."""
+    _, nz, ny, nx = S_n.shape
+    S_n = np.ascontiguousarray(S_n, dtype=np.float64)
+    lam_next = np.ascontiguousarray(lam_next, dtype=np.float64)
+    out = np.empty_like(S_n)
+    g = np.zeros((nz, ny, nx))
+    fx = None if Fx_field is None else np.ascontiguousarray(Fx_field, dtype=np.float64)
+    omega = 0.0 if np.isinf(tau) else 1.0 / tau
+    rc = _load().oracle_adjoint_step(nx, ny, nz, _fp(flags, (nz, ny, nx)), omega, _dp(_vec3(F)), _dp(fx),
+                                     _dp(S_n), _dp(lam_next), _dp(out), _dp(g))
+    if rc != 0:
+        raise MemoryError("oracle_adjoint_step: allocation failed")
+    return out, g
+
+
+def outlet_flux(S, F=None, flags=None, Fx_field=None):
+    """J = sum over the fluid sites of the plane x = nx - 1 of rho u_x
+    (= sum_i c_ix S_i - F_x / 2 there), for a stored state S."""
+    rho, u = macros(S, F=F, flags=flags, Fx_field=Fx_field)
+    return float((rho[:, :, -1] * u[0, :, :, -1]).sum())
+
+
+def grad_outlet_flux(S0, tau, nsteps, F=None, flags=None, Fx_field=None, every=None):
+    """J(S_nsteps) = outlet_flux after nsteps steps from S0, and dJ/dF_x for
+    every site (the per-site x-force is F[0] + Fx_field).  The forward states
+    are kept at every ``every`` steps (all of them when None) and each
+    segment is recomputed from its checkpoint for the backward sweep."""
+    _, nz, ny, nx = S0.shape
+    every = nsteps if every is None else int(every)
+    fx = np.zeros((nz, ny, nx)) if Fx_field is None else np.ascontiguousarray(Fx_field, dtype=np.float64)
+    C = lattice()[0]
+    fluid = np.ones((nz, ny, nx), bool) if flags is None else flags == 0
+    checkpoints = {}
+    S = np.array(S0, dtype=np.float64, copy=True)
+    for n in range(nsteps):
+        if n % every == 0:
+            checkpoints[n] = S.copy()
+        S = step(S, tau, F=F, flags=flags, Fx_field=fx)
+    J = outlet_flux(S, F=F, flags=flags, Fx_field=fx)
+    # seed: dJ/dS_N = c_ix at the outlet's fluid sites; direct term -1/2 per outlet site
+    lam = np.zeros_like(S)
+    out_mask = np.zeros((nz, ny, nx), bool)
+    out_mask[:, :, -1] = fluid[:, :, -1]
+    for i in range(Q):
+        lam[i][out_mask] = C[i, 0]
+    grad = np.zeros((nz, ny, nx))
+    grad[out_mask] -= 0.5
+    for start in sorted(checkpoints, reverse=True):
+        stop = min(start + every, nsteps)
+        states = [checkpoints[start]]
+        for n in range(start, stop - 1):
+            states.append(step(states[-1], tau, F=F, flags=flags, Fx_field=fx))
+        for n in range(stop - 1, start - 1, -1):
+            lam, g = adjoint_step(states[n - start], lam, tau, F=F, flags=flags, Fx_field=fx)
+            grad += g
+    return J, grad
 
 
 def run_window(rho, u, flags, tau, nsteps, centres, F=None, shape=None, fields=None):

@@ -267,3 +267,139 @@ void oracle_sums(int nx, int ny, int nz, const uint8_t *flags, const double *S, 
     }
     for (int k = 0; k < 4; ++k) out[k] = acc[k];
 }
+
+/* ------------------------------------------------------------------------- *
+ * Adjoint of the fused step (reverse-mode derivative).
+ *
+ * One step maps the stored state S_n to S_{n+1} = C(P S_n, F): P is the pull
+ * streaming with halfway bounce-back (step 1 above), C the per-site
+ * collision with the Guo source (steps 2-5).  For an objective J(S_N) the
+ * adjoint state lam_n = dJ/dS_n obeys
+ *     lam_n = P^T ( (dC/df)^T lam_{n+1} ),
+ * and the force enters every step through C, so
+ *     dJ/dF_x(x) = sum_n (dC/dF_x)(x)^T lam_{n+1}(x)   (+ any direct term of J).
+ *
+ * dC/df at one site, with rho = sum f, u = (sum c f + F/2) / rho:
+ *   dC_i/df_j = (1 - omega) delta_ij
+ *             + omega [ dfeq_i/drho + sum_a dfeq_i/du_a (c_ja - u_a) / rho ]
+ *             + sum_a dS_i/du_a (c_ja - u_a) / rho
+ *   dfeq_i/drho = w_i (1 + 3 c_i.u + 9/2 (c_i.u)^2 - 3/2 u.u)
+ *   dfeq_i/du_a = w_i rho (3 c_ia + 9 (c_i.u) c_ia - 3 u_a)
+ *   dS_i/du_a   = (1 - omega/2) w_i (9 (c_i.F) c_ia - 3 F_a)
+ * and, since du_x/dF_x = 1 / (2 rho),
+ *   dC_i/dF_x = [omega dfeq_i/du_x + dS_i/du_x] / (2 rho)
+ *             + (1 - omega/2) w_i (3 (c_ix - u_x) + 9 (c_i.u) c_ix).
+ *
+ * P^T: P reads S_k(y) exactly once, at site y + c_k for direction k when
+ * that site is fluid, else at site y itself for direction opp(k) (bounce-back
+ * at the solid y + c_k).  So, for a fluid site y,
+ *     (P^T m)_k(y) = m_k(y + c_k)     if y + c_k is fluid,
+ *                  = m_opp(k)(y)      otherwise.
+ * ------------------------------------------------------------------------- */
+
+/*
+ * Jacobian of the collision at one site: J[i*Q + j] = dC_i/df_j for the
+ * pre-collision populations f (unshifted) and force density F (3 values);
+ * dFx[i] = dC_i/dF_x.
+ */
+void oracle_collision_jacobian(double omega, const double *f, const double *F, double *J, double *dFx)
+{
+    double rho = 0.0, mom[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < Q; ++i) {
+        rho += f[i];
+        for (int a = 0; a < 3; ++a) mom[a] += LATTICE_C[i][a] * f[i];
+    }
+    double u[3];
+    for (int a = 0; a < 3; ++a) u[a] = (mom[a] + 0.5 * F[a]) / rho;
+    double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    for (int i = 0; i < Q; ++i) {
+        double w = lattice_w(i);
+        double cu = LATTICE_C[i][0] * u[0] + LATTICE_C[i][1] * u[1] + LATTICE_C[i][2] * u[2];
+        double cF = LATTICE_C[i][0] * F[0] + LATTICE_C[i][1] * F[1] + LATTICE_C[i][2] * F[2];
+        double dfeq_drho = w * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+        double dfeq_du[3], dS_du[3];
+        for (int a = 0; a < 3; ++a) {
+            dfeq_du[a] = w * rho * (3.0 * LATTICE_C[i][a] + 9.0 * cu * LATTICE_C[i][a] - 3.0 * u[a]);
+            dS_du[a] = (1.0 - 0.5 * omega) * w * (9.0 * cF * LATTICE_C[i][a] - 3.0 * F[a]);
+        }
+        for (int j = 0; j < Q; ++j) {
+            double v = (i == j ? 1.0 - omega : 0.0) + omega * dfeq_drho;
+            for (int a = 0; a < 3; ++a) {
+                double du = (LATTICE_C[j][a] - u[a]) / rho;
+                v += (omega * dfeq_du[a] + dS_du[a]) * du;
+            }
+            J[i * Q + j] = v;
+        }
+        dFx[i] = (omega * dfeq_du[0] + dS_du[0]) / (2.0 * rho)
+                 + (1.0 - 0.5 * omega) * w * (3.0 * (LATTICE_C[i][0] - u[0]) + 9.0 * cu * LATTICE_C[i][0]);
+    }
+}
+
+/*
+ * Adjoint of one step taken from S_n: lam_out = dJ/dS_n from lam_next =
+ * dJ/dS_{n+1} (both 19N, same layout as S; solid sites of lam_out are 0),
+ * and grad_fx[s] += dJ/dF_x(s) through this step (N values, fluid sites).
+ * F / Fx_field as in oracle_step.  Returns 0, or -1 on allocation failure.
+ */
+int oracle_adjoint_step(int nx, int ny, int nz, const uint8_t *flags, double omega, const double *F,
+                        const double *Fx_field, const double *S_n, const double *lam_next, double *lam_out,
+                        double *grad_fx)
+{
+    size_t N = (size_t)nx * ny * nz;
+    double *m = (double *)calloc((size_t)Q * N, sizeof(double));
+    if (!m) return -1;
+    /* m = (dC/df)^T lam_next at every fluid site */
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                size_t s = (size_t)x + (size_t)nx * ((size_t)y + (size_t)ny * z);
+                if (flags && flags[s]) continue;
+                double f[Q];
+                for (int i = 0; i < Q; ++i) {
+                    int xs = wrap(x - LATTICE_C[i][0], nx);
+                    int ys = wrap(y - LATTICE_C[i][1], ny);
+                    int zs = wrap(z - LATTICE_C[i][2], nz);
+                    size_t src = (size_t)xs + (size_t)nx * ((size_t)ys + (size_t)ny * zs);
+                    if (flags && flags[src])
+                        f[i] = S_n[(size_t)lattice_opp(i) * N + s];
+                    else
+                        f[i] = S_n[(size_t)i * N + src];
+                }
+                double force[3] = {F ? F[0] : 0.0, F ? F[1] : 0.0, F ? F[2] : 0.0};
+                if (Fx_field) force[0] += Fx_field[s];
+                double J[Q * Q], dFx[Q];
+                oracle_collision_jacobian(omega, f, force, J, dFx);
+                double g = 0.0;
+                for (int j = 0; j < Q; ++j) {
+                    double acc = 0.0;
+                    for (int i = 0; i < Q; ++i) acc += lam_next[(size_t)i * N + s] * J[i * Q + j];
+                    m[(size_t)j * N + s] = acc;
+                }
+                for (int i = 0; i < Q; ++i) g += lam_next[(size_t)i * N + s] * dFx[i];
+                if (grad_fx) grad_fx[s] += g;
+            }
+    /* lam_out = P^T m */
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                size_t s = (size_t)x + (size_t)nx * ((size_t)y + (size_t)ny * z);
+                for (int k = 0; k < Q; ++k) {
+                    if (flags && flags[s]) {
+                        lam_out[(size_t)k * N + s] = 0.0;
+                        continue;
+                    }
+                    int xt = wrap(x + LATTICE_C[k][0], nx);
+                    int yt = wrap(y + LATTICE_C[k][1], ny);
+                    int zt = wrap(z + LATTICE_C[k][2], nz);
+                    size_t t = (size_t)xt + (size_t)nx * ((size_t)yt + (size_t)ny * zt);
+                    if (flags && flags[t])
+                        lam_out[(size_t)k * N + s] = m[(size_t)lattice_opp(k) * N + s];
+                    else
+                        lam_out[(size_t)k * N + s] = m[(size_t)k * N + t];
+                }
+            }
+    free(m);
+    return 0;
+}
