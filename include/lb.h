@@ -200,6 +200,37 @@ int lb_time_step_kernel(lb_lattice *lat, int n, double *ms);
  */
 int lb_copy_probe(lb_lattice *lat, int reps, double *ms);
 
+/* ---- differentiation ----------------------------------------------------- */
+
+/*
+ * Per-site x-force: fx is a caller-owned DEVICE array of N floats (site
+ * order), copied; from now on the force density of site s is
+ * (F_x + fx[s], F_y, F_z) in the collision (Guo source and half-force
+ * velocity shift, Eq. 1) and in lb_macros.  NULL removes the field.
+ * FP32 storage only.  The copy is enqueued on the lattice's stream.
+ */
+int lb_set_force_field(lb_lattice *lat, const float *fx);
+
+/*
+ * Gradient of an objective of the final state with respect to the per-site
+ * x-force, by the adjoint of the fused step (reverse mode: the transposed
+ * collision Jacobian of BGK with Guo forcing and the transposed pull
+ * streaming with bounce-back, one fused kernel per step).
+ * The call advances the lattice by nsteps steps exactly as lb_step does
+ * (state, step count and totals), keeping a copy of the state every `every`
+ * steps, then sweeps backwards: each stretch of `every` steps is recomputed
+ * from its copy and differentiated.  seed: caller-owned DEVICE array of
+ * 19 * N floats in the raw-state layout of lb_get_f holding dJ/dS_N, the
+ * derivative of the objective with respect to the final stored state (zero
+ * at solid sites).  grad: caller-owned DEVICE array of N floats, overwritten
+ * with sum over the steps of dJ/dF_x(s) through the collisions; a term of J
+ * that depends on the force directly is the caller's to add.  FP32 storage.
+ * Device memory for ceil(nsteps / every) + min(every, nsteps) + 2 states is
+ * allocated during the call and freed before it returns; the call
+ * synchronises the stream.
+ */
+int lb_grad_force_x(lb_lattice *lat, int nsteps, int every, const float *seed, float *grad);
+
 /* ---- batches of lattices ------------------------------------------------- */
 
 /*
@@ -219,8 +250,9 @@ typedef struct lb_batch lb_batch;
  * 3d..3d+2, each >= 1.  taus: HOST double[count], each > 0.5 or +INFINITY.
  * flags: NULL (every domain all fluid) or a HOST array of count pointers,
  * each NULL (all fluid) or nx*ny*nz bytes of 0 (fluid) / 1 (solid), copied.
- * storage: LB_F32, LB_F16S or LB_BF16S.  hip_stream: a borrowed hipStream_t
- * or NULL for a stream the batch creates.  autotune: 0 = the default launch
+ * storage: LB_F32, LB_F16S or LB_BF16S.  hip_stream: the hipStream_t on
+ * which all of the batch's work is enqueued (borrowed, as in lb_create_ex;
+ * NULL is the default stream).  autotune: 0 = the default launch
  * shape (16-byte vectors of population rows, storage blocks of 32 KiB per
  * population, one workgroup per tile); 1 = time every candidate shape (sites
  * per lane, storage block size, grid size, tile order) on this batch once

@@ -46,6 +46,8 @@ _SIGNATURES = {
     "lb_time_steps": (ctypes.c_int, [_P, ctypes.c_int, _P]),
     "lb_time_step_kernel": (ctypes.c_int, [_P, ctypes.c_int, _P]),
     "lb_copy_probe": (ctypes.c_int, [_P, ctypes.c_int, _P]),
+    "lb_set_force_field": (ctypes.c_int, [_P, _P]),
+    "lb_grad_force_x": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _P]),
     "lb_batch_create": (_P, [ctypes.c_int, _P, _P, _P, ctypes.c_int, _P, ctypes.c_int]),
     "lb_batch_destroy": (None, [_P]),
     "lb_batch_set_force": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
@@ -210,6 +212,30 @@ class Lattice:
     def sync(self):
         _check(lib().lb_sync(self._h), "lb_sync")
 
+    def set_force_field(self, fx=None):
+        """Per-site x-force (float32 CUDA tensor (nz, ny, nx)) added to the
+        uniform one; None removes it.  FP32 storage."""
+        import torch
+
+        if fx is not None:
+            if fx.dtype != torch.float32 or not fx.is_cuda or not fx.is_contiguous() or \
+                    tuple(fx.shape) != (self.nz, self.ny, self.nx):
+                raise ValueError("expected a contiguous float32 CUDA tensor of shape (nz, ny, nx)")
+        self._fx_field = fx
+        _check(lib().lb_set_force_field(self._h, _ptr(fx)), "lb_set_force_field")
+
+    def grad_force_x(self, nsteps: int, every: int, seed):
+        """Advance nsteps steps and return dJ/dF_x (float32 (nz, ny, nx)) for
+        an objective with dJ/dS_N = seed (float32 CUDA tensor (19, nz, ny, nx))."""
+        import torch
+
+        if seed.dtype != torch.float32 or not seed.is_cuda or not seed.is_contiguous() or \
+                tuple(seed.shape) != (19, self.nz, self.ny, self.nx):
+            raise ValueError("seed must be a contiguous float32 CUDA tensor of shape (19, nz, ny, nx)")
+        grad = torch.empty((self.nz, self.ny, self.nx), dtype=torch.float32, device="cuda")
+        _check(lib().lb_grad_force_x(self._h, int(nsteps), int(every), _ptr(seed), _ptr(grad)), "lb_grad_force_x")
+        return grad
+
     @property
     def steps_done(self) -> int:
         return int(lib().lb_steps_done(self._h))
@@ -238,6 +264,68 @@ class Lattice:
         ms = ctypes.c_double(0.0)
         _check(lib().lb_copy_probe(self._h, int(reps), ctypes.byref(ms)), "lb_copy_probe")
         return ms.value
+
+
+C_X = np.array([0, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1, 0, 0, 0, 0])
+
+
+def outlet_flux(lat: "Lattice"):
+    """J = sum of rho u_x over the fluid sites of the plane x = nx - 1 (a
+    float64 CUDA scalar), from the lattice's current state."""
+    rho, u = lat.macros()
+    return (rho[:, :, -1].double() * u[0, :, :, -1].double()).sum()
+
+
+def outlet_flux_seed(lat: "Lattice", fluid):
+    """dJ/dS_N of the outlet flux: c_ix at the fluid sites of x = nx - 1.
+    fluid: bool CUDA tensor (nz, ny, nx)."""
+    import torch
+
+    seed = torch.zeros((19, lat.nz, lat.ny, lat.nx), dtype=torch.float32, device="cuda")
+    cx = torch.tensor(C_X, dtype=torch.float32, device="cuda")
+    seed[:, :, :, -1] = cx[:, None, None] * fluid[None, :, :, -1].float()
+    return seed
+
+
+def _outlet_flux_function():
+    import torch
+
+    class OutletFlux(torch.autograd.Function):
+        """J(fx) = outlet flux after ``nsteps`` steps from the lattice's
+        current state with per-site x-force field fx.  The backward pass
+        restores the saved initial state and runs lb_grad_force_x
+        (checkpointed recomputation every ``every`` steps, adjoint kernels);
+        the lattice is left at step nsteps after either pass."""
+
+        @staticmethod
+        def forward(ctx, fx, lat, nsteps, every, fluid):
+            state0 = torch.empty((19, lat.nz, lat.ny, lat.nx), dtype=torch.float32, device="cuda")
+            lat.get_f_device(state0)
+            lat.set_force_field(fx.detach().contiguous())
+            lat.step(nsteps)
+            J = outlet_flux(lat)
+            ctx.lat, ctx.nsteps, ctx.every = lat, nsteps, every
+            ctx.save_for_backward(fx.detach(), state0, fluid)
+            return J
+
+        @staticmethod
+        def backward(ctx, gJ):
+            fx, state0, fluid = ctx.saved_tensors
+            lat = ctx.lat
+            lat.set_f_device(state0)
+            lat.set_force_field(fx.contiguous())
+            g = lat.grad_force_x(ctx.nsteps, ctx.every, outlet_flux_seed(lat, fluid))
+            g = g.double()
+            g[:, :, -1] -= 0.5 * fluid[:, :, -1].double()  # J holds -F_x / 2 at each outlet site
+            return (gJ * g).to(fx.dtype), None, None, None, None
+
+    return OutletFlux
+
+
+def outlet_flux_autograd(fx, lat: "Lattice", nsteps: int, every: int, fluid):
+    """Differentiable outlet flux: torch.autograd sees J as a function of the
+    per-site x-force fx (float32 CUDA tensor (nz, ny, nx))."""
+    return _outlet_flux_function().apply(fx, lat, int(nsteps), int(every), fluid)
 
 
 class Batch:

@@ -81,8 +81,7 @@ struct lb_batch {
     int ntiles = 0, grid = 0, cus = 0;
     int cur = 0;
     long long steps = 0;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
+    hipStream_t stream = nullptr;  // borrowed (NULL: the default stream)
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t gexec = nullptr;
     bool graph_ok = false;
@@ -136,8 +135,7 @@ void release_all(lb_batch *b)
     free_dev(b->counter);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     b->cap_stream = nullptr;
-    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
-    b->stream = nullptr;
+    b->stream = nullptr;  // borrowed
 }
 
 StepArgs domain_args(const lb_batch *b, const Domain &d)
@@ -463,13 +461,7 @@ lb_batch *lb_batch_create(int count, const int *dims, const double *taus, const 
         return nullptr;
     };
     hipError_t e;
-    if (hip_stream) {
-        b->stream = static_cast<hipStream_t>(hip_stream);
-    } else {
-        if ((e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking)) != hipSuccess)
-            return bail(LB_EHIP, "hipStreamCreate", e);
-        b->own_stream = true;
-    }
+    b->stream = static_cast<hipStream_t>(hip_stream);  // NULL: the default stream (as lb_create_ex)
     int dev = 0;
     hipDeviceProp_t prop;
     if ((e = hipGetDevice(&dev)) != hipSuccess || (e = hipGetDeviceProperties(&prop, dev)) != hipSuccess)

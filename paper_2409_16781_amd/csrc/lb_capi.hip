@@ -7,6 +7,7 @@
 // long step sequences are replayed from a captured HIP graph.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -67,6 +68,7 @@ struct lb_lattice {
     void *alloc[2];   // allocations holding buf[0], buf[1] (buf[b] may sit at an offset)
     int cur;          // buf[cur] holds the state
     uint8_t *flags;   // device copy, or nullptr when all fluid
+    float *ffield;    // per-site x-force added to force[0] (device, N floats), or nullptr
     uint32_t *nbmask;
     uint8_t *rowdirty;
     bool solids;
@@ -120,6 +122,7 @@ StepArgs step_args(const lb_lattice *h, int from, float *rho, float *u)
     a.rho_out = rho;
     a.u_out = u;
     a.partials = h->partials;
+    a.fx_field = h->ffield;
     return a;
 }
 
@@ -211,8 +214,8 @@ void release(lb_lattice *h)
 {
     if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
-    void *ptrs[] = {h->alloc[0], h->alloc[1], h->flags,     h->nbmask, h->rowdirty,
-                    h->partials, h->gpartials, h->ticket, h->ring,     h->counter};
+    void *ptrs[] = {h->alloc[0], h->alloc[1], h->flags,   h->nbmask, h->rowdirty, h->partials,
+                    h->gpartials, h->ticket,  h->ring,    h->counter, h->ffield};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -449,10 +452,134 @@ int lb_macros(lb_lattice *h, float *rho, float *u)
     a.fy = (float)h->force[1];
     a.fz = (float)h->force[2];
     a.flags = h->flags;
+    a.fx_field = h->ffield;
     a.rho = rho;
     a.u = u;
     HIP_OR_FAIL(launch_macros(h->codec, a, h->stream));
     return LB_OK;
+}
+
+int lb_set_force_field(lb_lattice *h, const float *fx)
+{
+    if (int rc = check(h)) return rc;
+    if (!fx) {
+        HIP_OR_FAIL(hipStreamSynchronize(h->stream));
+        if (h->ffield) (void)hipFree(h->ffield);
+        h->ffield = nullptr;
+        h->graph_ok = false;
+        return LB_OK;
+    }
+    if (h->codec != kF32) return fail(LB_EINVAL, "force fields need FP32 storage");
+    if (!h->ffield) {
+        hipError_t e = hipMalloc(&h->ffield, h->n * sizeof(float) + 64);
+        if (e != hipSuccess) {
+            h->ffield = nullptr;
+            return fail(LB_ENOMEM, "hipMalloc(force field): %s", hipGetErrorString(e));
+        }
+    }
+    HIP_OR_FAIL(hipMemcpyAsync(h->ffield, fx, h->n * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
+    // the field is read as whole vectors of the row kernels: any nx works with one site per lane
+    if (h->variant == 0) {
+        h->variant = 3;
+        h->vsites = sites_per_thread(h->codec, 3);
+        const uint64_t tiles = (h->n / h->vsites + kBlock - 1) / kBlock;
+        h->grid = (int)std::min<uint64_t>(tiles, 0x7fffffffull);
+        HIP_OR_FAIL(hipStreamSynchronize(h->stream));
+        (void)hipFree(h->partials);
+        (void)hipFree(h->gpartials);
+        h->partials = h->gpartials = nullptr;
+        const size_t ngroups = ((size_t)h->grid + kRedChunk - 1) / kRedChunk;
+        if (hipMalloc(&h->partials, (size_t)h->grid * 4 * sizeof(double)) != hipSuccess ||
+            hipMalloc(&h->gpartials, ngroups * 4 * sizeof(double)) != hipSuccess)
+            return fail(LB_ENOMEM, "hipMalloc(partials)");
+    }
+    h->graph_ok = false;
+    return LB_OK;
+}
+
+int lb_grad_force_x(lb_lattice *h, int nsteps, int every, const float *seed, float *grad)
+{
+    if (int rc = check(h)) return rc;
+    if (h->codec != kF32) return fail(LB_EINVAL, "the adjoint needs FP32 storage");
+    if (nsteps < 1 || every < 1) return fail(LB_EINVAL, "nsteps and every must be >= 1");
+    if (!seed || !grad) return fail(LB_EINVAL, "seed and grad must be device pointers");
+    if (h->variant == 0) return fail(LB_EINVAL, "the adjoint runs the row kernels: set a force field first");
+    const size_t abytes = (size_t)h->arr_elems * sizeof(float);
+    const int nck = (nsteps + every - 1) / every;
+    const int seg = std::min(every, nsteps);
+    // device memory of the sweep: checkpoints, one segment of states, two adjoint arrays
+    std::vector<void *> mem;
+    auto grab = [&](size_t bytes) -> void * {
+        void *p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+        mem.push_back(p);
+        return p;
+    };
+    auto cleanup = [&]() {
+        (void)hipStreamSynchronize(h->stream);
+        for (void *p : mem) (void)hipFree(p);
+    };
+    std::vector<char *> ck(nck), states(seg);
+    for (int k = 0; k < nck; ++k) ck[k] = static_cast<char *>(grab(abytes));
+    for (int k = 1; k < seg; ++k) states[k] = static_cast<char *>(grab(abytes));
+    char *nu[2] = {static_cast<char *>(grab(abytes)), static_cast<char *>(grab(abytes))};
+    char *lamN = static_cast<char *>(grab(abytes));
+    for (void *p : mem)
+        if (!p) {
+            cleanup();
+            return fail(LB_ENOMEM, "hipMalloc of the adjoint sweep (%d checkpoints of %zu bytes)", nck, abytes);
+        }
+    if ((int)mem.size() != nck + (seg - 1) + 3) {
+        cleanup();
+        return fail(LB_ENOMEM, "hipMalloc of the adjoint sweep (%d checkpoints of %zu bytes)", nck, abytes);
+    }
+    int rc = LB_OK;
+    auto hip = [&](hipError_t e, const char *what) {
+        if (rc == LB_OK && e != hipSuccess) rc = fail(LB_EHIP, "%s: %s", what, hipGetErrorString(e));
+    };
+    // forward: checkpoints, then the ordinary steps (the lattice ends at step nsteps)
+    for (int n = 0; n < nsteps && rc == LB_OK; ++n) {
+        if (n % every == 0)
+            hip(hipMemcpyAsync(ck[n / every], h->buf[h->cur], abytes, hipMemcpyDeviceToDevice, h->stream), "checkpoint");
+        if (rc == LB_OK) rc = enqueue_one(h, h->cur, nullptr, nullptr, h->stream);
+        if (rc == LB_OK) {
+            h->cur ^= 1;
+            h->steps += 1;
+        }
+    }
+    // seed (raw planes) into the storage layout; zero the gradient
+    if (rc == LB_OK) hip(hipMemsetAsync(lamN, 0, abytes, h->stream), "hipMemsetAsync");
+    if (rc == LB_OK) hip(launch_repack(const_cast<float *>(seed), lamN, h->lay, (int64_t)h->n, 4, true, h->stream), "seed");
+    if (rc == LB_OK) hip(hipMemsetAsync(grad, 0, h->n * sizeof(float), h->stream), "hipMemsetAsync");
+    if (rc == LB_OK) hip(hipMemsetAsync(nu[0], 0, abytes, h->stream), "hipMemsetAsync");
+    if (rc == LB_OK) hip(hipMemsetAsync(nu[1], 0, abytes, h->stream), "hipMemsetAsync");
+    // backward, segment by segment from the last; each segment is recomputed
+    // from its checkpoint (recomputed steps write no totals)
+    int cur_nu = 0;
+    bool first = true;
+    for (int k = nck - 1; k >= 0 && rc == LB_OK; --k) {
+        const int start = k * every, stop = std::min(start + every, nsteps);
+        states[0] = ck[k];
+        for (int j = 1; j < stop - start && rc == LB_OK; ++j) {
+            StepArgs a = step_args(h, 0, nullptr, nullptr);
+            a.src = states[j - 1];
+            a.dst = states[j];
+            hip(launch_step(h->codec, h->variant, h->solids, false, a, h->grid, h->stream), "recompute step");
+        }
+        for (int n = stop - 1; n >= start && rc == LB_OK; --n) {
+            AdjArgs a{};
+            a.s = step_args(h, 0, nullptr, nullptr);
+            a.state = states[n - start];
+            a.lam_in = first ? static_cast<const void *>(lamN) : nu[cur_nu];
+            a.nu_out = nu[cur_nu ^ 1];
+            a.grad = grad;
+            hip(launch_adjoint(h->variant, first, a, h->grid, h->stream), "adjoint step");
+            first = false;
+            cur_nu ^= 1;
+        }
+    }
+    cleanup();
+    return rc;
 }
 
 int lb_sums(lb_lattice *h, double *out, int k)

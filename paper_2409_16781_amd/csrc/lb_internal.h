@@ -83,6 +83,7 @@ struct StepArgs {
     float *rho_out;           // optional macros output (N floats) or nullptr
     float *u_out;             // optional macros output (3N floats) or nullptr
     double *partials;         // out: 4 doubles per workgroup
+    const float *fx_field;    // optional per-site x-force added to coll.fx (N floats, site order) or nullptr
 };
 
 // One lattice of a batch.  The step arguments of domain d are s, with the
@@ -116,6 +117,15 @@ struct BatchTotalsArgs {
     unsigned long long *step_counter;
 };
 
+// One adjoint step (FP32 storage): see adjoint_vec in lb_kernels.hip.
+struct AdjArgs {
+    StepArgs s;               // geometry, masks, collision constants, force field
+    const void *state;        // S_n, the stored state the step starts from
+    const void *lam_in;       // first step: dJ/dS_N (read at each site); else nu_{n+1}
+    void *nu_out;             // nu_n = (dC/df)^T lam_{n+1}
+    float *grad;              // N floats (site order): += dJ/dF_x of this step
+};
+
 // The reduction of one step's partials into the ring of per-step totals.
 struct TotalsArgs {
     const double *partials;   // 4 doubles per step workgroup
@@ -141,6 +151,7 @@ struct MacroArgs {
     Layout lay;
     int n;
     float fx, fy, fz;
+    const float *fx_field;    // per-site x-force added to fx (N floats) or nullptr
     const uint8_t *flags;
     float *rho;
     float *u;
@@ -174,6 +185,8 @@ long env_long(const char *name, long dflt);  // integer environment setting (tun
 // Batches: variant 1 / 2 / 3 as above (always with bounce-back masks).
 hipError_t launch_batch_step(int codec, int variant, const BatchArgs &a, int grid, hipStream_t s);
 hipError_t launch_batch_totals(const BatchTotalsArgs &a, hipStream_t s);
+// One adjoint step; variant 1 / 2 / 3 = 4 / 2 / 1 sites per lane (FP32 storage).
+hipError_t launch_adjoint(int variant, bool first, const AdjArgs &a, int grid, hipStream_t s);
 int batch_occupancy(int codec, int variant);
 // Raw planes (19 x n elements of esize bytes, site order) to the storage
 // layout (to_state) or back.  Both pointers are device pointers.

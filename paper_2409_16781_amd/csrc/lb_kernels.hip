@@ -556,45 +556,61 @@ struct EdgeLds {
     uint32_t wave_last[kBlock / 64][5], wave_first[kBlock / 64][5];
 };
 
-// One tile (kBlock lanes, V sites each) of lattice a: gather with periodic
-// wrap and bounce-back, collide, store into dst, and add the FP64 totals of
-// the tile's fluid sites to acc.  NW: dwords per lane and population (16-,
-// 8- or 4-byte accesses).  kPadded: rows are stored with pitch > nx (a whole
-// number of vectors); the sites x >= nx of a row are held at zero like solid
-// sites and take no part in the totals.
-template <int C, int NW, bool kSolids, bool kMacros, bool kPadded>
-__device__ __forceinline__ void tile_update(const StepArgs &a, const char *src, char *dst, int tile,
-                                            double (&acc)[4], EdgeLds &lds)
+// Where the lanes of one tile sit: a lane owns V consecutive sites of one
+// stored row (row = y + ny z), starting at x0.
+struct TileGeom {
+    bool active;              // the lane's slot exists (else it repeats the last slot)
+    uint32_t s0;              // stored index of the first site (row * pitch + x0)
+    uint32_t row, x0, y, z, ym, yp, zm, zp;
+    uint64_t own;             // element offset of the first site, population 0
+};
+
+template <int V, bool kPadded>
+__device__ __forceinline__ TileGeom tile_geom(const StepArgs &a, int tile)
 {
-    using K = Codec<C>;
-    constexpr int V = NW * 4 / K::kBytes;  // sites per lane
-    static_assert(!(kPadded && kMacros), "same-pass macros are written for unpadded rows");
-    const Coll &cp = a.coll;
+    TileGeom g;
     const uint32_t nx = (uint32_t)a.nx, ny = (uint32_t)a.ny, nz = (uint32_t)a.nz;
     const uint32_t pitch = kPadded ? a.lay.pitch : nx;
-    const int lane = threadIdx.x & 63;
-
     const int slot = tile * kBlock + (int)threadIdx.x;
-    const bool active = slot < a.nslots;
-    const uint32_t s0 = (uint32_t)(active ? slot : a.nslots - 1) * V;  // stored index of the first site
-    const uint32_t row = fastdiv(s0, a.div_pitch);
-    const uint32_t x0 = s0 - row * pitch;
-    const uint32_t z = fastdiv(row, a.div_ny);
-    const uint32_t y = row - z * ny;
-    const uint32_t ym = (y == 0 ? ny : y) - 1, yp = (y + 1 == ny) ? 0 : y + 1;
-    const uint32_t zm = (z == 0 ? nz : z) - 1, zp = (z + 1 == nz) ? 0 : z + 1;
+    g.active = slot < a.nslots;
+    g.s0 = (uint32_t)(g.active ? slot : a.nslots - 1) * V;
+    g.row = fastdiv(g.s0, a.div_pitch);
+    g.x0 = g.s0 - g.row * pitch;
+    g.z = fastdiv(g.row, a.div_ny);
+    g.y = g.row - g.z * ny;
+    g.ym = (g.y == 0 ? ny : g.y) - 1;
+    g.yp = (g.y + 1 == ny) ? 0 : g.y + 1;
+    g.zm = (g.z == 0 ? nz : g.z) - 1;
+    g.zp = (g.z + 1 == nz) ? 0 : g.z + 1;
+    g.own = a.lay.row_base(g.row) + g.x0;
+    return g;
+}
+
+// Pull gather of the 19 populations of a tile's sites from the stored array
+// src, with periodic wrap and halfway bounce-back: d[i] = src_i(x - c_i), or
+// src_opp(i)(x) where x - c_i is solid.  kSwap gathers the transpose used by
+// the adjoint instead: d[i] = src_opp(i)(x - c_i), or src_i(x) where x - c_i
+// is solid (that is the value of population opp(i) of the transposed
+// streaming).  Returns the lane's dead sites (bit e: site e is solid, or
+// padding when kPadded).
+template <int C, int NW, bool kSolids, bool kPadded, bool kSwap>
+__device__ __forceinline__ uint32_t gather(const StepArgs &a, const char *src, const TileGeom &g, Lane<NW> (&d)[kQ],
+                                           EdgeLds &lds)
+{
+    using K = Codec<C>;
+    constexpr int V = NW * 4 / K::kBytes;
+    const uint32_t nx = (uint32_t)a.nx, ny = (uint32_t)a.ny;
+    const int lane = threadIdx.x & 63;
+    const uint32_t x0 = g.x0;
 
     // start (element offset) of the pulled source row of each population
     uint64_t rb[kQ];
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
-        const uint32_t ys = CY[i] > 0 ? ym : (CY[i] < 0 ? yp : y);
-        const uint32_t zs = CZ[i] > 0 ? zm : (CZ[i] < 0 ? zp : z);
-        rb[i] = a.lay.row_base(zs * ny + ys) + (uint64_t)i * a.lay.seg;
+        const uint32_t ys = CY[i] > 0 ? g.ym : (CY[i] < 0 ? g.yp : g.y);
+        const uint32_t zs = CZ[i] > 0 ? g.zm : (CZ[i] < 0 ? g.zp : g.z);
+        rb[i] = a.lay.row_base(zs * ny + ys) + (uint64_t)(kSwap ? OPP[i] : i) * a.lay.seg;
     }
-    const uint64_t own = a.lay.row_base(row) + x0;  // this lane's first site, population 0
-
-    Lane<NW> d[kQ];
 #pragma unroll
     for (int i = 0; i < kQ; ++i) d[i] = ldv<NW>(src + (rb[i] + x0) * K::kBytes);
 
@@ -610,7 +626,7 @@ __device__ __forceinline__ void tile_update(const StepArgs &a, const char *src, 
     const int wave = threadIdx.x >> 6;
     const int rit = (int)threadIdx.x >> a.lg_row_lanes;  // row within the tile
     if (a.lds_edges) {
-        __syncthreads();  // the previous tile's readers are done
+        __syncthreads();  // the previous readers are done
         if (row_end) {
 #pragma unroll
             for (int k = 0; k < 5; ++k) lds.row_last[rit][k] = d[kPlusX[k]].w[NW - 1];
@@ -668,17 +684,16 @@ __device__ __forceinline__ void tile_update(const StepArgs &a, const char *src, 
         }
     }
 
-    // halfway bounce-back: where x - c_i is solid, take the site's own opp(i)
-    // value.  dead: bit e set if site e of this lane is solid (or padding).
+    // halfway bounce-back: where x - c_i is solid, take the site's own value
     uint32_t dead = 0;
     if constexpr (kPadded) {
 #pragma unroll
         for (int e = 1; e < V; ++e) dead |= (x0 + e >= nx ? 1u : 0u) << e;
     }
     if constexpr (kSolids) {
-        if (a.rowdirty[row]) {
+        if (a.rowdirty[g.row]) {
             uint32_t m[V];
-            load_masks<V>(a.nbmask + s0, m);
+            load_masks<V>(a.nbmask + g.s0, m);
 #pragma unroll
             for (int e = 0; e < V; ++e) dead |= (m[e] >> 31) << e;
 #pragma unroll
@@ -687,7 +702,7 @@ __device__ __forceinline__ void tile_update(const StepArgs &a, const char *src, 
 #pragma unroll
                 for (int e = 0; e < V; ++e) sel |= ((m[e] >> i) & 1u) << e;
                 if (sel) {
-                    const Lane<NW> o = ldv<NW>(src + (own + OPP[i] * a.lay.seg) * K::kBytes);
+                    const Lane<NW> o = ldv<NW>(src + (g.own + (kSwap ? i : OPP[i]) * a.lay.seg) * K::kBytes);
 #pragma unroll
                     for (int e = 0; e < V; ++e)
                         if ((sel >> e) & 1u) vset<C, NW>(d[i], e, vget<C, NW>(o, e));
@@ -695,18 +710,66 @@ __device__ __forceinline__ void tile_update(const StepArgs &a, const char *src, 
             }
         }
     }
+    return dead;
+}
+
+// Collision constants of one site whose x-force is fx (the per-site force
+// field added to the uniform one); y and z forces stay uniform.
+__device__ __forceinline__ Coll coll_at(const Coll &p, float fx)
+{
+    Coll q = p;
+    q.fx = fx;
+    q.hfx = 0.5f * fx;
+#pragma unroll
+    for (int i = 1; i < kQ; ++i) {
+        const float cF = (float)CX[i] * fx + (float)CY[i] * p.fy + (float)CZ[i] * p.fz;
+        const float g3 = weight_class(i) == 1 ? p.g31 : p.g32;  // 3 (1 - omega/2) w_i
+        q.hC[i] = 3.0f * g3 * cF;
+        q.hD[i] = g3 * cF;
+    }
+    return q;
+}
+
+// One tile (kBlock lanes, V sites each) of lattice a: gather with periodic
+// wrap and bounce-back, collide, store into dst, and add the FP64 totals of
+// the tile's fluid sites to acc.  kPadded: rows are stored with pitch > nx
+// (a whole number of vectors); the sites x >= nx of a row are held at zero
+// like solid sites and take no part in the totals.  kFField: the x-force of
+// each site is the uniform one plus a per-site field (a.fx_field).
+template <int C, int NW, bool kSolids, bool kMacros, bool kPadded, bool kFField = false>
+__device__ __forceinline__ void tile_update(const StepArgs &a, const char *src, char *dst, int tile,
+                                            double (&acc)[4], EdgeLds &lds)
+{
+    using K = Codec<C>;
+    constexpr int V = NW * 4 / K::kBytes;  // sites per lane
+    static_assert(!(kPadded && kMacros), "same-pass macros are written for unpadded rows");
+    static_assert(!kFField || (K::kBytes == 4 && !kPadded), "force fields: FP32 storage, unpadded rows");
+    const Coll &cp = a.coll;
+    const TileGeom g = tile_geom<V, kPadded>(a, tile);
+    Lane<NW> d[kQ];
+    const uint32_t dead = gather<C, NW, kSolids, kPadded, false>(a, src, g, d, lds);
 
     // collide site by site (16-bit codecs: two sites per dword at a time)
     float mr[V], mu[V], mv[V], mw[V];
     if constexpr (K::kBytes == 4) {
+        float fxs[V];
+        if constexpr (kFField) {
+            load_masks<V>(reinterpret_cast<const uint32_t *>(a.fx_field) + g.s0,
+                          reinterpret_cast<uint32_t(&)[V]>(fxs));
+        }
 #pragma unroll
         for (int e = 0; e < V; ++e) {
-            float g[kQ];
+            float gg[kQ];
 #pragma unroll
-            for (int i = 0; i < kQ; ++i) g[i] = K::dec(d[i].w[e]);
-            collide(g, cp, mr[e], mu[e], mv[e], mw[e]);
+            for (int i = 0; i < kQ; ++i) gg[i] = K::dec(d[i].w[e]);
+            if constexpr (kFField) {
+                const Coll q = coll_at(cp, cp.fx + fxs[e]);
+                collide(gg, q, mr[e], mu[e], mv[e], mw[e]);
+            } else {
+                collide(gg, cp, mr[e], mu[e], mv[e], mw[e]);
+            }
 #pragma unroll
-            for (int i = 0; i < kQ; ++i) d[i].w[e] = K::enc(g[i]);
+            for (int i = 0; i < kQ; ++i) d[i].w[e] = K::enc(gg[i]);
         }
     } else {
 #pragma unroll
@@ -721,7 +784,7 @@ __device__ __forceinline__ void tile_update(const StepArgs &a, const char *src, 
         }
     }
 
-    if (active) {
+    if (g.active) {
         // Solid (and padding) sites hold zero in both arrays: they are
         // written as zero inside a vector with fluid sites (whole-vector
         // stores) and not at all in an all-solid vector.  The zeros add
@@ -740,14 +803,14 @@ __device__ __forceinline__ void tile_update(const StepArgs &a, const char *src, 
         }
         if (dead != (1u << V) - 1u) {
 #pragma unroll
-            for (int i = 0; i < kQ; ++i) stv<NW>(dst + (own + i * a.lay.seg) * K::kBytes, d[i]);
+            for (int i = 0; i < kQ; ++i) stv<NW>(dst + (g.own + i * a.lay.seg) * K::kBytes, d[i]);
         }
         if constexpr (kMacros) {
-            const size_t n = (size_t)nx * ny * nz;
-            store_floats<V>(a.rho_out + s0, mr);
-            store_floats<V>(a.u_out + s0, mu);
-            store_floats<V>(a.u_out + n + s0, mv);
-            store_floats<V>(a.u_out + 2 * n + s0, mw);
+            const size_t n = (size_t)a.nx * a.ny * a.nz;
+            store_floats<V>(a.rho_out + g.s0, mr);
+            store_floats<V>(a.u_out + g.s0, mu);
+            store_floats<V>(a.u_out + n + g.s0, mv);
+            store_floats<V>(a.u_out + 2 * n + g.s0, mw);
         }
         // totals of the values as stored (after rounding), fluid sites only
         float tot[kQ];
@@ -772,9 +835,136 @@ __device__ __forceinline__ void tile_update(const StepArgs &a, const char *src, 
     }
 }
 
+// ------------------------------------------------------------ adjoint --
+// Reverse-mode derivative of one step (FP32 storage).  A step maps the
+// stored state S_n to S_{n+1} = C(P S_n): P is the pull streaming with
+// bounce-back, C the per-site BGK collision with Guo forcing (Eq. 1-3).  For
+// an objective J(S_N) the adjoint lam_n = dJ/dS_n obeys lam_n = P^T nu_n with
+// nu_n = (dC/df)^T lam_{n+1} at every site, where f = P S_n.  The kernel of
+// step n gathers lam_{n+1} = P^T nu_{n+1} (the transposed pull of the
+// previous adjoint array; for the last step lam_N is read at the site
+// itself), gathers f from S_n, and writes nu_n.  With rho, u the moments of f
+// (u with the half-force shift), w_i the weights and F the site's force:
+//   nu_j = (1 - omega) lam_j + A + B.(c_j - u) / rho
+//   A    = omega sum_i lam_i w_i (1 + 3 c_i.u + 9/2 (c_i.u)^2 - 3/2 u.u)
+//   B    = sum_i lam_i w_i c_i [3 omega rho + 9 omega rho c_i.u + 9 (1 - omega/2) c_i.F]
+//          - 3 (omega rho u + (1 - omega/2) F) sum_i lam_i w_i
+// (A and B are lam contracted with dfeq/drho and with dfeq/du + dS/du), and
+// the x-force of the site receives
+//   dJ/dF_x += B_x / (2 rho) + (1 - omega/2)(3 sum_i lam_i w_i c_ix
+//              - 3 u_x sum_i lam_i w_i + 9 sum_i lam_i w_i (c_i.u) c_ix).
+// Solid sites keep nu = 0 and no gradient.
+
+template <int NW, bool kFirst, bool kSolids>
+__global__ __launch_bounds__(kBlock) void adjoint_vec(AdjArgs a)
+{
+    using K = Codec<kF32>;
+    constexpr int V = NW;
+    __shared__ EdgeLds lds;
+    const StepArgs &sa = a.s;
+    const Coll &cp = sa.coll;
+    const float om = 2.0f * cp.hom;        // omega
+    const float k1 = 1.0f - cp.hom;        // 1 - omega/2
+    const char *state = reinterpret_cast<const char *>(a.state);
+    const char *lam_src = reinterpret_cast<const char *>(a.lam_in);
+    char *nu_out = reinterpret_cast<char *>(a.nu_out);
+    const int ntiles = (sa.nslots + kBlock - 1) / kBlock;
+    for (int b = blockIdx.x; b < ntiles; b += gridDim.x) {
+        const TileGeom g = tile_geom<V, false>(sa, b);
+        Lane<NW> d[kQ];
+        const uint32_t dead = gather<kF32, NW, kSolids, false, false>(sa, state, g, d, lds);
+        // moments of the pulled pre-collision populations (shifted storage)
+        float rho[V], ux[V], uy[V], uz[V], fx[V];
+        float fxf[V];
+        if (sa.fx_field)
+            load_masks<V>(reinterpret_cast<const uint32_t *>(sa.fx_field) + g.s0, reinterpret_cast<uint32_t(&)[V]>(fxf));
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            float gg[kQ];
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) gg[i] = K::dec(d[i].w[e]);
+            float dr = 0.0f, jx = 0.0f, jy = 0.0f, jz = 0.0f;
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) {
+                dr += gg[i];
+                if (CX[i]) jx += CX[i] * gg[i];
+                if (CY[i]) jy += CY[i] * gg[i];
+                if (CZ[i]) jz += CZ[i] * gg[i];
+            }
+            fx[e] = cp.fx + (sa.fx_field ? fxf[e] : 0.0f);
+            rho[e] = 1.0f + dr;
+            const float inv = 1.0f / rho[e];
+            ux[e] = (jx + 0.5f * fx[e]) * inv;
+            uy[e] = (jy + cp.hfy) * inv;
+            uz[e] = (jz + cp.hfz) * inv;
+        }
+        // adjoint of the next state at this step's sites
+        if constexpr (kFirst) {
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) d[i] = ldv<NW>(lam_src + (g.own + i * sa.lay.seg) * K::kBytes);
+        } else {
+            (void)gather<kF32, NW, kSolids, false, true>(sa, lam_src, g, d, lds);
+        }
+        float gF[V];
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            float lam[kQ];
+#pragma unroll
+            for (int k = 0; k < kQ; ++k) lam[k] = K::dec(kFirst ? d[k].w[e] : d[OPP[k]].w[e]);
+            const float r = rho[e], u0 = ux[e], u1 = uy[e], u2 = uz[e];
+            const float uu = u0 * u0 + u1 * u1 + u2 * u2;
+            const float F0 = fx[e], F1 = cp.fy, F2 = cp.fz;
+            const float orr = om * r;
+            float Lw = 0.0f, A = 0.0f, B0 = 0.0f, B1 = 0.0f, B2 = 0.0f, G0 = 0.0f, H0 = 0.0f;
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) {
+                const float w = weight_class(i) == 0 ? 1.0f / 3.0f : (weight_class(i) == 1 ? W1 : W2);
+                const float lw = lam[i] * w;
+                const float cu = CX[i] * u0 + CY[i] * u1 + CZ[i] * u2;
+                const float cF = CX[i] * F0 + CY[i] * F1 + CZ[i] * F2;
+                Lw += lw;
+                A += lw * (1.0f + 3.0f * cu + 4.5f * cu * cu - 1.5f * uu);
+                const float t = lw * (3.0f * orr + 9.0f * orr * cu + 9.0f * k1 * cF);
+                if (CX[i]) {
+                    B0 += CX[i] * t;
+                    G0 += CX[i] * lw;
+                    H0 += CX[i] * lw * cu;
+                }
+                if (CY[i]) B1 += CY[i] * t;
+                if (CZ[i]) B2 += CZ[i] * t;
+            }
+            A *= om;
+            B0 -= 3.0f * (orr * u0 + k1 * F0) * Lw;
+            B1 -= 3.0f * (orr * u1 + k1 * F1) * Lw;
+            B2 -= 3.0f * (orr * u2 + k1 * F2) * Lw;
+            const float inv = 1.0f / r;
+            gF[e] = 0.5f * B0 * inv + k1 * (3.0f * G0 - 3.0f * u0 * Lw + 9.0f * H0);
+            const float base = A - (B0 * u0 + B1 * u1 + B2 * u2) * inv;
+#pragma unroll
+            for (int j = 0; j < kQ; ++j) {
+                const float cB = CX[j] * B0 + CY[j] * B1 + CZ[j] * B2;
+                const float nu = (1.0f - om) * lam[j] + base + cB * inv;
+                d[j].w[e] = K::enc((dead >> e) & 1u ? 0.0f : nu);
+            }
+        }
+        if (g.active) {
+            if (dead != (1u << V) - 1u) {
+#pragma unroll
+                for (int i = 0; i < kQ; ++i) stv<NW>(nu_out + (g.own + i * sa.lay.seg) * K::kBytes, d[i]);
+                float gr[V];
+                load_masks<V>(reinterpret_cast<const uint32_t *>(a.grad) + g.s0, reinterpret_cast<uint32_t(&)[V]>(gr));
+#pragma unroll
+                for (int e = 0; e < V; ++e)
+                    if (!((dead >> e) & 1u)) gr[e] += gF[e];
+                store_floats<V>(a.grad + g.s0, gr);
+            }
+        }
+    }
+}
+
 // One step of one lattice: one workgroup per tile (or a capped grid looping
 // over tiles); each workgroup stores the FP64 totals of its tiles.
-template <int C, int NW, bool kSolids, bool kMacros>
+template <int C, int NW, bool kSolids, bool kMacros, bool kFField = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(vec_waves<C, NW>()))) void step_vec(StepArgs a)
 {
     __shared__ EdgeLds lds;
@@ -783,7 +973,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(vec_wave
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     const int ntiles = (a.nslots + kBlock - 1) / kBlock;
     for (int b = blockIdx.x; b < ntiles; b += gridDim.x)
-        tile_update<C, NW, kSolids, kMacros, false>(a, src, dst, tile_of(b, ntiles, a.tile_order), acc, lds);
+        tile_update<C, NW, kSolids, kMacros, false, kFField>(a, src, dst, tile_of(b, ntiles, a.tile_order), acc, lds);
     store_block_totals(acc, a.partials + 4 * (size_t)blockIdx.x);
 }
 
@@ -978,7 +1168,8 @@ __global__ __launch_bounds__(kBlock) void macros_kernel(MacroArgs a)
             moments_of_totals(g, m, px, py, pz);
             r = 1.0f + m;
             const float inv = 1.0f / r;
-            ux = (px - 0.5f * a.fx) * inv;
+            const float fxs = a.fx + (a.fx_field ? a.fx_field[s] : 0.0f);
+            ux = (px - 0.5f * fxs) * inv;
             uy = (py - 0.5f * a.fy) * inv;
             uz = (pz - 0.5f * a.fz) * inv;
         }
@@ -1075,8 +1266,20 @@ void *step_fn(int variant)
     return reinterpret_cast<void *>(&step_site<C, S, M>);
 }
 
-void *pick_step(int codec, int variant, bool solids, bool macros)
+template <bool S, bool M>
+void *ffield_fn(int variant)
 {
+    if (variant == 1) return reinterpret_cast<void *>(&step_vec<kF32, 4, S, M, true>);
+    if (variant == 2) return reinterpret_cast<void *>(&step_vec<kF32, 2, S, M, true>);
+    return reinterpret_cast<void *>(&step_vec<kF32, 1, S, M, true>);
+}
+
+void *pick_step(int codec, int variant, bool solids, bool macros, bool ffield)
+{
+    if (ffield) {  // FP32 storage, vector-row variants only (checked by the caller)
+        if (solids) return macros ? ffield_fn<true, true>(variant) : ffield_fn<true, false>(variant);
+        return macros ? ffield_fn<false, true>(variant) : ffield_fn<false, false>(variant);
+    }
 #define LB_PICK(C)                                                                                 \
     if (solids) return macros ? step_fn<C, true, true>(variant) : step_fn<C, true, false>(variant); \
     return macros ? step_fn<C, false, true>(variant) : step_fn<C, false, false>(variant);
@@ -1126,7 +1329,7 @@ int sites_per_thread(int codec, int variant)
 int step_occupancy(int codec, int variant, bool solids, bool macros)
 {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pick_step(codec, variant, solids, macros), kBlock, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pick_step(codec, variant, solids, macros, false), kBlock, 0) !=
         hipSuccess)
         return 1;
     return nb < 1 ? 1 : nb;
@@ -1134,7 +1337,7 @@ int step_occupancy(int codec, int variant, bool solids, bool macros)
 
 hipError_t launch_step(int codec, int variant, bool solids, bool macros, const StepArgs &a, int grid, hipStream_t s)
 {
-    void *fn = pick_step(codec, variant, solids, macros);
+    void *fn = pick_step(codec, variant, solids, macros, a.fx_field != nullptr);
     StepArgs arg = a;
     void *params[] = {&arg};
     return hipLaunchKernel(fn, dim3(grid), dim3(kBlock), params, 0, s);
@@ -1190,6 +1393,30 @@ int batch_occupancy(int codec, int variant)
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pick_batch(codec, variant), kBlock, 0) != hipSuccess) return 1;
     return nb < 1 ? 1 : nb;
+}
+
+namespace {
+template <int NW, bool S>
+void *adjoint_fn(bool first)
+{
+    return first ? reinterpret_cast<void *>(&adjoint_vec<NW, true, S>) : reinterpret_cast<void *>(&adjoint_vec<NW, false, S>);
+}
+template <bool S>
+void *pick_adjoint(int variant, bool first)
+{
+    if (variant == 1) return adjoint_fn<4, S>(first);
+    if (variant == 2) return adjoint_fn<2, S>(first);
+    return adjoint_fn<1, S>(first);
+}
+}  // namespace
+
+hipError_t launch_adjoint(int variant, bool first, const AdjArgs &a, int grid, hipStream_t s)
+{
+    const bool solids = a.s.nbmask != nullptr;
+    void *fn = solids ? pick_adjoint<true>(variant, first) : pick_adjoint<false>(variant, first);
+    AdjArgs arg = a;
+    void *params[] = {&arg};
+    return hipLaunchKernel(fn, dim3(grid), dim3(kBlock), params, 0, s);
 }
 
 hipError_t launch_totals(const TotalsArgs &a, hipStream_t s)

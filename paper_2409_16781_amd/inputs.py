@@ -167,6 +167,16 @@ def batch_domains(count: int = 64, nmin: int = 16, nmax: int = 96, porosity: flo
     return out
 
 
+def porous_channel(n: int = 128, porosity: float = 0.85, tau: float = 0.6, g: float = 1e-6, seed: int = 4,
+                   steps: int = 500, every: int = 50):
+    """n^3 porous channel for the force gradient: walls at y = 0 and n-1 plus
+    random spheres (radius U[2, 6], seed) to the given porosity, uniform force
+    (g, 0, 0), at rest initially (rho = 1, u = 0)."""
+    flags = sphere_flags(n, n, n, porosity, seed, rmin=2.0, rmax=6.0, walls=True)
+    return dict(name=f"porous{n}", shape=(n, n, n), rho=np.ones((n, n, n)), u=np.zeros((3, n, n, n)),
+                flags=flags, tau=tau, force=(g, 0.0, 0.0), steps=steps, every=every)
+
+
 def tgv_noise_box(n: int = 512, u0: float = 0.01, tau: float = 0.55, steps: int = 1000,
                   noise: float = 1e-3, seed: int = 2):
     """Periodic n^3 Taylor-Green vortex plus i.i.d. U(+-noise) on every velocity component."""

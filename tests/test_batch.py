@@ -161,8 +161,9 @@ def test_totals_per_domain_match_oracle(mixed_ref):
         tot = b.sums(k, 1)[0]
         ref = oracle.sums(S, d["flags"])
         assert abs(tot[0] - ref[0]) <= 1e-6 * ref[0], (k, tot, ref)
+        # totals of the FP32-rounded state: relative differences of order 1e-7
         for c in (1, 2, 3):
-            assert abs(tot[c] - ref[c]) <= 1e-7 * max(1.0, abs(ref[c])) + 1e-9, (k, c, tot, ref)
+            assert abs(tot[c] - ref[c]) <= 1e-6 * max(1.0, abs(ref[c])), (k, c, tot, ref)
     b.close()
 
 
