@@ -43,6 +43,7 @@ def parse():
     p.add_argument("--reps", type=int, default=3, help="timed repetitions (median reported)")
     p.add_argument("--no-batch", action="store_true", help="skip the 64-domain batch leg")
     p.add_argument("--batch-steps", type=int, default=500, help="timed steps of the batch leg")
+    p.add_argument("--no-adjoint", action="store_true", help="skip the 128^3 force-gradient leg")
     return p.parse_args()
 
 
@@ -150,6 +151,42 @@ def run_batch(torch, lbm, steps, reps):
                 finite_totals=bool(np.all(np.isfinite(sums))))
 
 
+def run_adjoint(torch, lbm, reps):
+    """Gradient of the outlet mass flux of a 128^3 porous channel (porosity
+    0.85) with respect to the per-site x-force: 500 forward steps with a copy
+    every 50, recomputation and 500 adjoint steps (FP32 storage)."""
+    from paper_2409_16781_amd import inputs
+    cfg = inputs.porous_channel(128, porosity=0.85, tau=0.6, g=1e-6, seed=4, steps=500, every=50)
+    n = 128
+    lat = lbm.Lattice(n, n, n, cfg["tau"], flags=cfg["flags"])
+    lat.set_force(*cfg["force"])
+    fluid = torch.from_numpy(cfg["flags"] == 0).cuda()
+    rho = torch.from_numpy(cfg["rho"]).cuda()
+    u = torch.from_numpy(cfg["u"]).cuda()
+    lat.set_force_field(torch.zeros((n, n, n), dtype=torch.float32, device="cuda"))
+    lat.init_eq(rho, u)
+    seed = lbm.outlet_flux_seed(lat, fluid)
+    lat.grad_force_x(20, 10, seed)  # warm-up
+    times = []
+    for _ in range(reps):
+        lat.init_eq(rho, u)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = lat.grad_force_x(cfg["steps"], cfg["every"], seed)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    dt = sorted(times)[len(times) // 2]
+    fl = int(fluid.sum())
+    lat.close()
+    return dict(workload="128^3 porous channel (porosity 0.85, seed 4), tau=0.6, force 1e-6, gradient of the outlet "
+                         "mass flux w.r.t. the per-site x-force, 500 steps, copies every 50, FP32",
+                sites=n ** 3, fluid_sites=fl, steps=cfg["steps"], every=cfg["every"],
+                ms_per_gradient=round(dt * 1e3, 3),
+                site_steps_per_s=round(3 * cfg["steps"] * n ** 3 / dt / 1e6, 1),
+                note="forward + recompute + adjoint = 3 x steps site updates; includes allocation of the copies",
+                finite=bool(torch.isfinite(g).all()))
+
+
 def cpu_baseline(cfg, steps):
     """The FP64 oracle as it stands, on the host cores, for a few steps of the same lattice."""
     import oracle
@@ -234,6 +271,10 @@ def main():
         line["batch64"] = run_batch(torch, lbm, args.batch_steps, args.reps)
         log(f"[bench] batch64: {line['batch64']['mlups_fluid']:.0f} fluid MLUPS, "
             f"{line['batch64']['achieved_gbs_fluid']:.0f} GB/s")
+    if not args.no_adjoint:
+        log("[bench] adjoint: 128^3 porous force gradient")
+        line["adjoint128"] = run_adjoint(torch, lbm, args.reps)
+        log(f"[bench] adjoint128: {line['adjoint128']['ms_per_gradient']:.1f} ms per gradient")
     if not args.no_cpu:
         log(f"[bench] CPU baseline: oracle, {args.cpu_steps} steps")
         line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_steps)
