@@ -95,8 +95,12 @@ int check(const lb_lattice *h)
     return LB_OK;
 }
 
-StepArgs step_args(const lb_lattice *h, int from, float *rho, float *u)
+// Arguments of a step (or adjoint step) of lattice h with the given kernel
+// variant (its sites per lane set the tiling; -1: the lattice's own).
+StepArgs step_args(const lb_lattice *h, int from, float *rho, float *u, int variant = -1)
 {
+    if (variant < 0) variant = h->variant;
+    const int vsites = sites_per_thread(h->codec, variant);
     StepArgs a{};
     a.src = h->buf[from];
     a.dst = h->buf[from ^ 1];
@@ -104,11 +108,11 @@ StepArgs step_args(const lb_lattice *h, int from, float *rho, float *u)
     a.nx = h->nx;
     a.ny = h->ny;
     a.nz = h->nz;
-    a.nslots = (int)(h->n / (uint64_t)h->vsites);
+    a.nslots = (int)(h->n / (uint64_t)vsites);
     // tiles of kBlock lanes hold whole rows when the lanes per row divide kBlock
-    const int row_lanes = h->nx / h->vsites;
+    const int row_lanes = h->nx / vsites;
     a.tile_order = h->tile_order;
-    a.lds_edges = (h->variant != 0 && h->nx % h->vsites == 0 && row_lanes <= kBlock && (kBlock % row_lanes) == 0 &&
+    a.lds_edges = (variant != 0 && h->nx % vsites == 0 && row_lanes <= kBlock && (kBlock % row_lanes) == 0 &&
                    env_long("LB_LDS_EDGES", 1) != 0)
                       ? 1
                       : 0;
@@ -504,6 +508,14 @@ int lb_grad_force_x(lb_lattice *h, int nsteps, int every, const float *seed, flo
     if (nsteps < 1 || every < 1) return fail(LB_EINVAL, "nsteps and every must be >= 1");
     if (!seed || !grad) return fail(LB_EINVAL, "seed and grad must be device pointers");
     if (h->variant == 0) return fail(LB_EINVAL, "the adjoint runs the row kernels: set a force field first");
+    // sites per lane of the adjoint kernel: one (4-byte accesses; with its two
+    // gathers and the Jacobian the kernel then fits four waves per SIMD and
+    // ran fastest: 175 / 214 / 238 ms per 500-step 128^3 gradient with 1 / 2 /
+    // 4 sites per lane); LB_ADJ_KERNEL (1, 2, 3) overrides
+    int av = (int)env_long("LB_ADJ_KERNEL", 0);
+    if (av < 1 || av > 3) av = 3;
+    while (av < 3 && h->nx % sites_per_thread(kF32, av) != 0) ++av;
+    const int adj_grid = (int)std::min<uint64_t>((h->n / sites_per_thread(kF32, av) + kBlock - 1) / kBlock, 0x7fffffffull);
     const size_t abytes = (size_t)h->arr_elems * sizeof(float);
     const int nck = (nsteps + every - 1) / every;
     const int seg = std::min(every, nsteps);
@@ -568,12 +580,12 @@ int lb_grad_force_x(lb_lattice *h, int nsteps, int every, const float *seed, flo
         }
         for (int n = stop - 1; n >= start && rc == LB_OK; --n) {
             AdjArgs a{};
-            a.s = step_args(h, 0, nullptr, nullptr);
+            a.s = step_args(h, 0, nullptr, nullptr, av);
             a.state = states[n - start];
             a.lam_in = first ? static_cast<const void *>(lamN) : nu[cur_nu];
             a.nu_out = nu[cur_nu ^ 1];
             a.grad = grad;
-            hip(launch_adjoint(h->variant, first, a, h->grid, h->stream), "adjoint step");
+            hip(launch_adjoint(av, first, a, adj_grid, h->stream), "adjoint step");
             first = false;
             cur_nu ^= 1;
         }
