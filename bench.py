@@ -44,6 +44,7 @@ def parse():
     p.add_argument("--no-batch", action="store_true", help="skip the 64-domain batch leg")
     p.add_argument("--batch-steps", type=int, default=500, help="timed steps of the batch leg")
     p.add_argument("--no-adjoint", action="store_true", help="skip the 128^3 force-gradient leg")
+    p.add_argument("--no-inplace", action="store_true", help="skip the one-array (in-place) FP32 leg")
     return p.parse_args()
 
 
@@ -149,6 +150,24 @@ def run_batch(torch, lbm, steps, reps):
                 shape={k: info[k] for k in ("variant", "sites_per_lane", "grid", "tiles", "tile_order", "seg_bytes",
                                              "grid_mult", "autotuned")},
                 finite_totals=bool(np.all(np.isfinite(sums))))
+
+
+def run_inplace(torch, lbm, cfg, steps, reps):
+    """The 512^3 workload with one population array (in-place update, FP32)."""
+    n = cfg["shape"][0]
+    lat = lbm.Lattice(n, n, n, cfg["tau"], codec="f32", inplace=True)
+    lat.init_eq(torch.from_numpy(cfg["rho"]).cuda(), torch.from_numpy(cfg["u"]).cuda())
+    torch.cuda.empty_cache()
+    lat.step(20)
+    lat.sync()
+    ms = sorted(lat.time_steps(steps) for _ in range(reps))[reps // 2]
+    k_even, k_odd = lat.time_step_kernel(1), lat.time_step_kernel(1)
+    info = lat.info
+    lat.close()
+    return dict(workload="same 512^3 workload, FP32, one population array (in-place update)",
+                mlups=round(n ** 3 * steps / (ms * 1e-3) / 1e6, 1), ms_per_step=round(ms / steps, 4),
+                kernel_ms_gather_push=round(k_even, 4), kernel_ms_local=round(k_odd, 4),
+                array_bytes=info["array_bytes"], arrays=1)
 
 
 def run_adjoint(torch, lbm, reps):
@@ -266,6 +285,10 @@ def main():
     }
     if "f16" in results and "f32" in results:
         line["f16_over_f32_mlups"] = round(results["f16"]["mlups"] / results["f32"]["mlups"], 3)
+    if not args.no_inplace and n == 512:
+        log("[bench] one-array (in-place) FP32")
+        line["inplace_f32"] = run_inplace(torch, lbm, cfg, args.steps, args.reps)
+        log(f"[bench] in-place f32: {line['inplace_f32']['mlups']:.0f} MLUPS")
     if not args.no_batch:
         log("[bench] batch of 64 porous domains (autotuned)")
         line["batch64"] = run_batch(torch, lbm, args.batch_steps, args.reps)

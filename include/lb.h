@@ -57,6 +57,19 @@ typedef struct lb_lattice lb_lattice;
 #define LB_F16S 1  /* FP16 storage of g = f - w, round-to-nearest-even        */
 #define LB_BF16S 2 /* BF16 storage of g = f - w, round-to-nearest-even        */
 
+/*
+ * Flag OR-ed into the storage argument of lb_create_ex: keep ONE population
+ * array instead of two (in-place update in the "AA" access pattern: steps
+ * alternate between one that gathers from the neighbours and pushes back to
+ * them and one that works at the site itself; every site reads and writes
+ * the same 19 locations, so no second array is needed).  Half the memory,
+ * the same bytes moved per step, results identical to two-array storage.
+ * Needs rows that tile whole: nx = V * 2^k with nx / V <= 256 for V in
+ * {4, 2, 1} (FP32) or {8, 4, 2} (16-bit codecs).  Not with force fields or
+ * the adjoint.
+ */
+#define LB_INPLACE 0x100
+
 /* Memory spaces for lb_get_f / lb_set_f. */
 #define LB_HOST 0
 #define LB_DEVICE 1
@@ -75,9 +88,9 @@ typedef struct lb_lattice lb_lattice;
 lb_lattice *lb_create(int nx, int ny, int nz, double tau, const uint8_t *flags);
 
 /*
- * As lb_create, with a storage codec (LB_F32, LB_F16S, LB_BF16S) and a HIP
- * stream (hipStream_t passed as void*) on which all of the lattice's work is
- * enqueued.  NULL is the default stream.  The stream is borrowed: the
+ * As lb_create, with a storage codec (LB_F32, LB_F16S, LB_BF16S, optionally
+ * OR-ed with LB_INPLACE) and a HIP stream (hipStream_t passed as void*) on
+ * which all of the lattice's work is enqueued.  NULL is the default stream.  The stream is borrowed: the
  * lattice never destroys it, and it must outlive the lattice.
  */
 lb_lattice *lb_create_ex(int nx, int ny, int nz, double tau, const uint8_t *flags, int storage,
@@ -118,7 +131,9 @@ int lb_step(lb_lattice *lat, int n);
  * As lb_step with n >= 1, and the last step also writes the density and
  * velocity it computes (the pre-collision moments of that step, u including
  * the half-force shift) into caller-owned device arrays rho (N floats) and u
- * (3N floats, component-major).  Solid sites get rho = 0, u = 0.
+ * (3N floats, component-major).  Solid sites get rho = 0, u = 0.  With
+ * in-place storage (LB_INPLACE) the fields come from the state just written,
+ * as lb_macros computes them (equal up to FP32 rounding).
  */
 int lb_step_macros(lb_lattice *lat, int n, float *rho, float *u);
 
@@ -172,7 +187,8 @@ long long lb_steps_done(const lb_lattice *lat);
  * and population), 1 = sites per thread, 2 = 1 if the lattice has solid
  * sites, 3 = bytes per stored population, 4 = workgroups per step launch,
  * 5 = x-rows per storage block, 6 = number of fluid sites, 7 = bytes of one
- * population array.  Returns -1 for an unknown key or a bad handle.
+ * population array, 8 = 1 for in-place (one-array) storage.  Returns -1 for
+ * an unknown key or a bad handle.
  */
 long long lb_query(const lb_lattice *lat, int key);
 

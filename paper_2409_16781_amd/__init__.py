@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(_PKG, "liblbm355.so")
 LB_OK, LB_EINVAL, LB_ENOMEM, LB_EHIP, LB_EUNSTABLE, LB_ESTATE = 0, -1, -2, -3, -4, -5
 LB_F32, LB_F16S, LB_BF16S = 0, 1, 2
 LB_HOST, LB_DEVICE = 0, 1
+LB_INPLACE = 0x100
 CODECS = {"f32": LB_F32, "f16": LB_F16S, "bf16": LB_BF16S}
 
 # Every function the C ABI exports, with its ctypes signature.
@@ -108,7 +109,8 @@ class Lattice:
     ``stream``: a torch.cuda.Stream, or None for torch's current stream.
     """
 
-    def __init__(self, nx: int, ny: int, nz: int, tau: float, flags=None, codec: str = "f32", stream=None):
+    def __init__(self, nx: int, ny: int, nz: int, tau: float, flags=None, codec: str = "f32", stream=None,
+                 inplace: bool = False):
         import torch
 
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
@@ -125,7 +127,8 @@ class Lattice:
         self._flags = fl
         h = lib().lb_create_ex(self.nx, self.ny, self.nz, float(tau),
                                None if fl is None else fl.ctypes.data_as(ctypes.c_void_p),
-                               CODECS[codec], ctypes.c_void_p(self._stream.cuda_stream))
+                               CODECS[codec] | (LB_INPLACE if inplace else 0),
+                               ctypes.c_void_p(self._stream.cuda_stream))
         if not h:
             raise LBError(LB_EINVAL, "lb_create_ex", last_error())
         self._h = ctypes.c_void_p(h)
@@ -246,7 +249,7 @@ class Lattice:
     @property
     def info(self) -> dict:
         keys = ["variant", "sites_per_thread", "solids", "bytes_per_population", "grid", "block_rows", "n_fluid",
-                "array_bytes"]
+                "array_bytes", "inplace"]
         return {k: self.query(i) for i, k in enumerate(keys)}
 
     def time_steps(self, n: int) -> float:

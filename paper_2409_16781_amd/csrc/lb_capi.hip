@@ -82,6 +82,7 @@ struct lb_lattice {
     hipStream_t cap_stream;
     int variant, vsites, grid, cus;
     int tile_order;
+    bool inplace;     // one population array (AA pattern); cur is then the phase (0 even, 1 odd)
     long long steps;
     hipGraphExec_t gexec;
     bool graph_ok;
@@ -113,7 +114,7 @@ StepArgs step_args(const lb_lattice *h, int from, float *rho, float *u, int vari
     const int row_lanes = h->nx / vsites;
     a.tile_order = h->tile_order;
     a.lds_edges = (variant != 0 && h->nx % vsites == 0 && row_lanes <= kBlock && (kBlock % row_lanes) == 0 &&
-                   env_long("LB_LDS_EDGES", 1) != 0)
+                   (h->inplace || env_long("LB_LDS_EDGES", 1) != 0))
                       ? 1
                       : 0;
     a.lg_row_lanes = 0;
@@ -127,6 +128,27 @@ StepArgs step_args(const lb_lattice *h, int from, float *rho, float *u, int vari
     a.u_out = u;
     a.partials = h->partials;
     a.fx_field = h->ffield;
+    return a;
+}
+
+// Arguments of the macros kernel for the state in buf[cur] (in-place
+// storage: the phase given by cur).
+MacroArgs macro_args(const lb_lattice *h, int cur, float *rho, float *u)
+{
+    MacroArgs a{};
+    a.src = h->buf[cur];
+    a.lay = h->lay;
+    a.n = (int)h->n;
+    a.ny = h->ny;
+    a.nz = h->nz;
+    a.aa_phase = h->inplace ? (cur == 0 ? 1 : 2) : 0;
+    a.fx = (float)h->force[0];
+    a.fy = (float)h->force[1];
+    a.fz = (float)h->force[2];
+    a.flags = h->flags;
+    a.fx_field = h->ffield;
+    a.rho = rho;
+    a.u = u;
     return a;
 }
 
@@ -148,6 +170,12 @@ int enqueue_one(lb_lattice *h, int from, float *rho, float *u, hipStream_t s)
 {
     const bool macros = rho != nullptr;
     StepArgs a = step_args(h, from, rho, u);
+    if (h->inplace) {
+        HIP_OR_FAIL(launch_aa_step(h->codec, h->variant, h->solids, from == 0, a, h->grid, s));
+        HIP_OR_FAIL(launch_totals(totals_args(h), s));
+        if (macros) HIP_OR_FAIL(launch_macros(h->codec, macro_args(h, from ^ 1, rho, u), s));
+        return LB_OK;
+    }
     HIP_OR_FAIL(launch_step(h->codec, h->variant, h->solids, macros, a, h->grid, s));
     HIP_OR_FAIL(launch_totals(totals_args(h), s));
     if (macros && h->solids && h->variant == 0)
@@ -232,6 +260,8 @@ int create_impl(lb_lattice **out, int nx, int ny, int nz, double tau, const uint
     const uint64_t n = (uint64_t)nx * ny * nz;
     if (n > 0x7fffffffull - 4096) return fail(LB_EINVAL, "lattice of %llu sites exceeds 2^31 - 4097", (unsigned long long)n);
     if (!(tau > 0.5)) return fail(LB_EINVAL, "tau must be > 0.5 or +inf (got %g)", tau);
+    const bool inplace = (storage & LB_INPLACE) != 0;
+    storage &= ~LB_INPLACE;
     if (storage != LB_F32 && storage != LB_F16S && storage != LB_BF16S)
         return fail(LB_EINVAL, "unknown storage codec %d", storage);
     uint64_t nsolid = 0;
@@ -257,6 +287,7 @@ int create_impl(lb_lattice **out, int nx, int ny, int nz, double tau, const uint
     h->stream = reinterpret_cast<hipStream_t>(stream);
     h->solids = nsolid > 0;
     h->n_fluid = (double)(n - nsolid);
+    h->inplace = inplace;
 
     // Step kernel: vector rows with 16-byte (FP32) or 8-byte (16-bit codecs)
     // accesses, 4 sites per lane; narrower vectors when nx is not a multiple
@@ -277,6 +308,22 @@ int create_impl(lb_lattice **out, int nx, int ny, int nz, double tau, const uint
         int v = variant + 1;
         while (v <= 3 && nx % sites_per_thread(storage, v) != 0) ++v;
         variant = v <= 3 ? v : 0;
+    }
+    if (inplace) {
+        // the in-place push exchanges x-edges inside a tile: whole rows per
+        // tile, i.e. nx / V a power of two of at most 256 lanes
+        auto rows_fit = [&](int v) {
+            if (v < 1 || v > 3) return false;
+            const int V = sites_per_thread(storage, v);
+            return nx % V == 0 && nx / V <= kBlock && kBlock % (nx / V) == 0;
+        };
+        int v = variant == 0 ? 1 : variant;
+        while (v <= 3 && !rows_fit(v)) ++v;
+        if (v > 3) {
+            delete h;
+            return fail(LB_EINVAL, "in-place storage needs nx = V * 2^k with nx / V <= 256 (V = sites per lane); got nx = %d", nx);
+        }
+        variant = v;
     }
     h->variant = variant;
     h->vsites = sites_per_thread(storage, h->variant);
@@ -338,7 +385,7 @@ int create_impl(lb_lattice **out, int nx, int ny, int nz, double tau, const uint
     if (ab_off < 0 || ab_off % 256 != 0) return bail(LB_EINVAL, "LB_AB_OFFSET", hipErrorInvalidValue);
     h->tile_order = env_long("LB_TILE_ORDER", 0) != 0 ? 1 : 0;
     hipError_t e;
-    for (int b = 0; b < 2; ++b) {
+    for (int b = 0; b < (h->inplace ? 1 : 2); ++b) {
         const size_t off = b == 1 ? (size_t)ab_off : 0;
         e = hipMalloc(&h->alloc[b], pbytes + off);
         if (e != hipSuccess) return bail(LB_ENOMEM, "hipMalloc(populations)", e);
@@ -346,6 +393,7 @@ int create_impl(lb_lattice **out, int nx, int ny, int nz, double tau, const uint
         e = hipMemsetAsync(h->buf[b], 0, pbytes, h->stream);
         if (e != hipSuccess) return bail(LB_EHIP, "hipMemsetAsync", e);
     }
+    if (h->inplace) h->buf[1] = h->buf[0];  // steps read and write the one array
     // per-step totals: one slot per step workgroup and one per reduce workgroup
     const size_t ngroups = ((size_t)h->grid + kRedChunk - 1) / kRedChunk;
     if ((e = hipMalloc(&h->partials, (size_t)h->grid * 4 * sizeof(double))) != hipSuccess) return bail(LB_ENOMEM, "hipMalloc", e);
@@ -423,6 +471,7 @@ int lb_init_eq(lb_lattice *h, const double *rho, const double *u)
     a.rho = rho;
     a.u = u;
     a.flags = h->flags;
+    a.swap = h->inplace ? 1 : 0;
     HIP_OR_FAIL(launch_init(h->codec, a, h->stream));
     HIP_OR_FAIL(hipMemsetAsync(h->counter, 0, sizeof(unsigned long long), h->stream));
     h->cur = 0;
@@ -448,18 +497,7 @@ int lb_step_macros(lb_lattice *h, int n, float *rho, float *u)
 int lb_macros(lb_lattice *h, float *rho, float *u)
 {
     if (int rc = check(h)) return rc;
-    MacroArgs a{};
-    a.src = h->buf[h->cur];
-    a.lay = h->lay;
-    a.n = (int)h->n;
-    a.fx = (float)h->force[0];
-    a.fy = (float)h->force[1];
-    a.fz = (float)h->force[2];
-    a.flags = h->flags;
-    a.fx_field = h->ffield;
-    a.rho = rho;
-    a.u = u;
-    HIP_OR_FAIL(launch_macros(h->codec, a, h->stream));
+    HIP_OR_FAIL(launch_macros(h->codec, macro_args(h, h->cur, rho, u), h->stream));
     return LB_OK;
 }
 
@@ -474,6 +512,7 @@ int lb_set_force_field(lb_lattice *h, const float *fx)
         return LB_OK;
     }
     if (h->codec != kF32) return fail(LB_EINVAL, "force fields need FP32 storage");
+    if (h->inplace) return fail(LB_EINVAL, "force fields need two-array storage");
     if (!h->ffield) {
         hipError_t e = hipMalloc(&h->ffield, h->n * sizeof(float) + 64);
         if (e != hipSuccess) {
@@ -505,6 +544,7 @@ int lb_grad_force_x(lb_lattice *h, int nsteps, int every, const float *seed, flo
 {
     if (int rc = check(h)) return rc;
     if (h->codec != kF32) return fail(LB_EINVAL, "the adjoint needs FP32 storage");
+    if (h->inplace) return fail(LB_EINVAL, "the adjoint needs two-array storage");
     if (nsteps < 1 || every < 1) return fail(LB_EINVAL, "nsteps and every must be >= 1");
     if (!seed || !grad) return fail(LB_EINVAL, "seed and grad must be device pointers");
     if (h->variant == 0) return fail(LB_EINVAL, "the adjoint runs the row kernels: set a force field first");
@@ -623,6 +663,33 @@ static int copy_f(lb_lattice *h, void *host_or_dev, size_t bytes, int where, boo
     if (bytes != want) return fail(LB_EINVAL, "buffer is %zu bytes, expected %zu", bytes, want);
     if (!host_or_dev) return fail(LB_EINVAL, "NULL buffer");
     if (where != LB_HOST && where != LB_DEVICE) return fail(LB_EINVAL, "where must be LB_HOST or LB_DEVICE");
+    if (h->inplace) {
+        // in-place storage: the state is rebuilt from (or written into) the
+        // array by a kernel; writing leaves the array in the even form
+        void *planes = host_or_dev;
+        hipError_t e = hipSuccess;
+        if (where == LB_HOST) {
+            e = hipMalloc(&planes, bytes);
+            if (e != hipSuccess) return fail(LB_ENOMEM, "hipMalloc(staging): %s", hipGetErrorString(e));
+            if (to_lattice) e = hipMemcpyAsync(planes, host_or_dev, bytes, hipMemcpyHostToDevice, h->stream);
+        }
+        if (e == hipSuccess)
+            e = launch_aa_planes(planes, h->buf[0], h->lay, h->ny, h->nz, h->flags, h->esize, h->cur == 0 ? 1 : 2,
+                                 to_lattice, h->stream);
+        if (e == hipSuccess && where == LB_HOST && !to_lattice)
+            e = hipMemcpyAsync(host_or_dev, planes, bytes, hipMemcpyDeviceToHost, h->stream);
+        if (where == LB_HOST) {
+            const hipError_t se = hipStreamSynchronize(h->stream);
+            (void)hipFree(planes);
+            if (e == hipSuccess) e = se;
+        }
+        if (e != hipSuccess) return fail(LB_EHIP, "population copy: %s", hipGetErrorString(e));
+        if (to_lattice) {
+            h->cur = 0;
+            h->graph_ok = false;
+        }
+        return LB_OK;
+    }
     // population i: full blocks as one 2-D copy (R rows per block), then the
     // rows of a last, partly filled block
     const size_t es = (size_t)h->esize;
@@ -687,6 +754,7 @@ long long lb_query(const lb_lattice *h, int key)
         case 5: return 1ll << h->lay.lg_r;
         case 6: return (long long)h->n_fluid;
         case 7: return (long long)(h->arr_elems * h->esize);
+        case 8: return h->inplace ? 1 : 0;
         default: return -1;
     }
 }
@@ -722,8 +790,9 @@ int lb_time_step_kernel(lb_lattice *h, int n, double *ms)
     for (int k = 0; k < n && rc == LB_OK; ++k) {
         StepArgs a = step_args(h, h->cur, nullptr, nullptr);
         if (hipEventRecord(ev[2 * k], h->stream) != hipSuccess) rc = fail(LB_EHIP, "hipEventRecord");
-        if (rc == LB_OK && launch_step(h->codec, h->variant, h->solids, false, a, h->grid, h->stream) != hipSuccess)
-            rc = fail(LB_EHIP, "step kernel launch");
+        const hipError_t le = h->inplace ? launch_aa_step(h->codec, h->variant, h->solids, h->cur == 0, a, h->grid, h->stream)
+                                         : launch_step(h->codec, h->variant, h->solids, false, a, h->grid, h->stream);
+        if (rc == LB_OK && le != hipSuccess) rc = fail(LB_EHIP, "step kernel launch");
         if (rc == LB_OK && hipEventRecord(ev[2 * k + 1], h->stream) != hipSuccess) rc = fail(LB_EHIP, "hipEventRecord");
         if (rc == LB_OK && launch_totals(totals_args(h), h->stream) != hipSuccess) rc = fail(LB_EHIP, "totals launch");
         if (rc == LB_OK) {

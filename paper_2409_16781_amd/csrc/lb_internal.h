@@ -144,12 +144,15 @@ struct InitArgs {
     const double *rho;        // N or nullptr
     const double *u;          // 3N or nullptr
     const uint8_t *flags;     // device flags or nullptr
+    int swap;                 // 1: population i goes to slot opp(i) (in-place storage, even phase)
 };
 
 struct MacroArgs {
     const void *src;
     Layout lay;
     int n;
+    int ny, nz;
+    int aa_phase;             // in-place storage: 1 even (swapped slots), 2 odd (pulled); 0: two arrays
     float fx, fy, fz;
     const float *fx_field;    // per-site x-force added to fx (N floats) or nullptr
     const uint8_t *flags;
@@ -192,6 +195,14 @@ int batch_occupancy(int codec, int variant);
 // layout (to_state) or back.  Both pointers are device pointers.
 hipError_t launch_repack(void *planes, void *state, const Layout &lay, int64_t n, int esize, bool to_state,
                          hipStream_t s);
+// In-place storage: raw planes of the state S from the array (phase 1 even,
+// 2 odd; flags may be nullptr), or planes into the array in the even form.
+hipError_t launch_aa_planes(void *planes, void *state, const Layout &lay, int ny, int nz, const uint8_t *flags,
+                            int esize, int phase, bool to_state, hipStream_t s);
+// In-place steps: even (true) runs the gather-collide-push kernel, odd the local one.
+hipError_t launch_aa_step(int codec, int variant, bool solids, bool from_even, const StepArgs &a, int grid,
+                          hipStream_t s);
+int aa_occupancy(int codec, int variant, bool solids, bool from_even);
 int sites_per_thread(int codec, int variant);
 
 }  // namespace lbm
