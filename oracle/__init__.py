@@ -29,6 +29,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "d3q19_oracle.c")
+_SRC2 = os.path.join(_HERE, "d2q9_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle_d3q19.so")
 
 Q = 19
@@ -38,7 +39,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc (FP64, no fast-math, no contraction)."""
     if force or not os.path.exists(_LIB):
         cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
-               "-fno-fast-math", "-Wall", "-o", _LIB, _SRC, "-lm"]
+               "-fno-fast-math", "-Wall", "-o", _LIB, _SRC, _SRC2, "-lm"]
         subprocess.run(cmd, check=True)
     return _LIB
 
@@ -66,6 +67,14 @@ def _load():
         lib.oracle_run.restype = ci
         lib.oracle_macros.argtypes = [ci, ci, ci, u8, d, d, d, d, d]
         lib.oracle_sums.argtypes = [ci, ci, ci, u8, d, d]
+        lib.oracle2_lattice.argtypes = [i32, d, i32]
+        lib.oracle2_feq.argtypes = [ctypes.c_double, d, d]
+        lib.oracle2_init.argtypes = [ci, ci, u8, d, d, d]
+        lib.oracle2_step.argtypes = [ci, ci, u8, ctypes.c_double, d, d, d]
+        lib.oracle2_run.argtypes = [ci, ci, u8, ctypes.c_double, d, d, ci]
+        lib.oracle2_run.restype = ci
+        lib.oracle2_macros.argtypes = [ci, ci, u8, d, d, d]
+        lib.oracle2_sums.argtypes = [ci, ci, u8, d, d]
         lib.oracle_collision_jacobian.argtypes = [ctypes.c_double, d, d, d, d]
         lib.oracle_adjoint_step.argtypes = [ci, ci, ci, u8, ctypes.c_double, d, d, d, d, d, d]
         lib.oracle_adjoint_step.restype = ci
@@ -243,6 +252,75 @@ def grad_outlet_flux(S0, tau, nsteps, F=None, flags=None, Fx_field=None, every=N
             lam, g = adjoint_step(states[n - start], lam, tau, F=F, flags=flags, Fx_field=fx)
             grad += g
     return J, grad
+
+
+# --------------------------------------------------------------- D2Q9 -------
+# The two-dimensional D2Q9 oracle (d2q9_oracle.c): state (9, ny, nx), flags
+# (ny, nx) with 0 fluid, 1 wall, 2 lid moving with velocity `lid`.
+
+Q2 = 9
+
+
+def d2_lattice():
+    c = np.zeros((Q2, 2), dtype=np.int32)
+    w = np.zeros(Q2)
+    opp = np.zeros(Q2, dtype=np.int32)
+    _load().oracle2_lattice(c.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _dp(w),
+                            opp.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+    return c, w, opp
+
+
+def d2_feq(rho, u):
+    out = np.zeros(Q2)
+    _load().oracle2_feq(float(rho), _dp(np.ascontiguousarray(np.asarray(u, np.float64).reshape(2))), _dp(out))
+    return out
+
+
+def d2_init(shape, rho=None, u=None, flags=None):
+    ny, nx = shape
+    S = np.zeros((Q2, ny, nx))
+    rho = None if rho is None else np.ascontiguousarray(rho, dtype=np.float64)
+    u = None if u is None else np.ascontiguousarray(u, dtype=np.float64)
+    _load().oracle2_init(nx, ny, _fp(flags, (ny, nx)), _dp(rho), _dp(u), _dp(S))
+    return S
+
+
+def _lid(lid):
+    return np.ascontiguousarray(np.asarray((0.0, 0.0) if lid is None else lid, np.float64).reshape(2))
+
+
+def d2_step(S, tau, flags=None, lid=None):
+    _, ny, nx = S.shape
+    S = np.ascontiguousarray(S, dtype=np.float64)
+    out = np.empty_like(S)
+    omega = 0.0 if np.isinf(tau) else 1.0 / tau
+    _load().oracle2_step(nx, ny, _fp(flags, (ny, nx)), omega, _dp(_lid(lid)), _dp(S), _dp(out))
+    return out
+
+
+def d2_run(S, tau, nsteps, flags=None, lid=None):
+    _, ny, nx = S.shape
+    S = np.array(S, dtype=np.float64, order="C", copy=True)
+    omega = 0.0 if np.isinf(tau) else 1.0 / tau
+    if _load().oracle2_run(nx, ny, _fp(flags, (ny, nx)), omega, _dp(_lid(lid)), _dp(S), int(nsteps)) != 0:
+        raise MemoryError("oracle2_run: allocation failed")
+    return S
+
+
+def d2_macros(S, flags=None):
+    _, ny, nx = S.shape
+    S = np.ascontiguousarray(S, dtype=np.float64)
+    rho = np.empty((ny, nx))
+    u = np.empty((2, ny, nx))
+    _load().oracle2_macros(nx, ny, _fp(flags, (ny, nx)), _dp(S), _dp(rho), _dp(u))
+    return rho, u
+
+
+def d2_sums(S, flags=None):
+    _, ny, nx = S.shape
+    out = np.zeros(3)
+    _load().oracle2_sums(nx, ny, _fp(flags, (ny, nx)), _dp(np.ascontiguousarray(S, np.float64)), _dp(out))
+    return out
 
 
 def run_window(rho, u, flags, tau, nsteps, centres, F=None, shape=None, fields=None):

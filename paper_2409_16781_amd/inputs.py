@@ -177,6 +177,28 @@ def porous_channel(n: int = 128, porosity: float = 0.85, tau: float = 0.6, g: fl
                 flags=flags, tau=tau, force=(g, 0.0, 0.0), steps=steps, every=every)
 
 
+def cavity_flags(nx: int, ny: int) -> np.ndarray:
+    """uint8 flags (ny, nx) of a lid-driven cavity: walls (1) at x = 0,
+    x = nx - 1 and y = 0; the lid (2) on the top row y = ny - 1 between the
+    corners, which are walls."""
+    f = np.zeros((ny, nx), dtype=np.uint8)
+    f[0, :] = 1
+    f[:, 0] = 1
+    f[:, nx - 1] = 1
+    f[ny - 1, 1:nx - 1] = 2
+    return f
+
+
+def lid_cavity(n: int = 4096, u0: float = 0.1, re: float = 1e4):
+    """The paper's lid-driven cavity (Section 3.3; n x n sites, Re = 1e4):
+    lid speed u0 along +x, viscosity from Re = u0 L / nu with L = n - 2 (the
+    fluid width between the halfway walls), tau = 3 nu + 1/2, at rest
+    initially."""
+    nu = u0 * (n - 2) / re
+    return dict(name=f"cavity{n}", shape=(n, n), flags=cavity_flags(n, n), tau=3.0 * nu + 0.5, lid=(u0, 0.0),
+                rho=None, u=None)
+
+
 def tgv_noise_box(n: int = 512, u0: float = 0.01, tau: float = 0.55, steps: int = 1000,
                   noise: float = 1e-3, seed: int = 2):
     """Periodic n^3 Taylor-Green vortex plus i.i.d. U(+-noise) on every velocity component."""
