@@ -45,6 +45,7 @@ def parse():
     p.add_argument("--batch-steps", type=int, default=500, help="timed steps of the batch leg")
     p.add_argument("--no-adjoint", action="store_true", help="skip the 128^3 force-gradient leg")
     p.add_argument("--no-inplace", action="store_true", help="skip the one-array (in-place) FP32 leg")
+    p.add_argument("--no-cavity", action="store_true", help="skip the 4096^2 D2Q9 lid-driven cavity leg")
     return p.parse_args()
 
 
@@ -206,6 +207,30 @@ def run_adjoint(torch, lbm, reps):
                 finite=bool(torch.isfinite(g).all()))
 
 
+def run_cavity2d(torch, lbm, steps, reps):
+    """The paper's own workload: D2Q9 lid-driven cavity, 4096^2 sites,
+    Re = 1e4, lid speed 0.1, FP32 storage of f - w, FP64 totals per step."""
+    from paper_2409_16781_amd import inputs
+    cfg = inputs.lid_cavity(4096)
+    ny, nx = cfg["shape"]
+    lat = lbm.Lattice2D(nx, ny, cfg["tau"], flags=cfg["flags"], lid=cfg["lid"])
+    lat.init_eq()
+    lat.step(50)
+    lat.sync()
+    ms = sorted(lat.time_steps(steps) for _ in range(reps))[reps // 2]
+    sums = lat.sums(min(steps, 1000))
+    n = nx * ny
+    fluid = int((cfg["flags"] == 0).sum())
+    lat.close()
+    return dict(workload=f"D2Q9 lid-driven cavity {nx}x{ny}, Re=1e4, lid 0.1, tau={cfg['tau']:.5f}, FP32",
+                mlups=round(n * steps / (ms * 1e-3) / 1e6, 1), mlups_fluid=round(fluid * steps / (ms * 1e-3) / 1e6, 1),
+                ms_per_step=round(ms / steps, 4), bytes_per_site=72,
+                achieved_gbs=round(72 * n * steps / (ms * 1e-3) / 1e9, 1),
+                frac_hbm=round(72 * n * steps / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                note="time per step includes the FP64 totals reduction kernel",
+                finite_totals=bool(np.all(np.isfinite(sums))))
+
+
 def cpu_baseline(cfg, steps):
     """The FP64 oracle as it stands, on the host cores, for a few steps of the same lattice."""
     import oracle
@@ -298,6 +323,11 @@ def main():
         log("[bench] adjoint: 128^3 porous force gradient")
         line["adjoint128"] = run_adjoint(torch, lbm, args.reps)
         log(f"[bench] adjoint128: {line['adjoint128']['ms_per_gradient']:.1f} ms per gradient")
+    if not args.no_cavity:
+        log("[bench] D2Q9 4096^2 lid-driven cavity")
+        line["cavity4096_d2q9"] = run_cavity2d(torch, lbm, 2 * args.steps, args.reps)
+        log(f"[bench] cavity4096: {line['cavity4096_d2q9']['mlups']:.0f} MLUPS, "
+            f"{line['cavity4096_d2q9']['achieved_gbs']:.0f} GB/s")
     if not args.no_cpu:
         log(f"[bench] CPU baseline: oracle, {args.cpu_steps} steps")
         line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_steps)

@@ -328,6 +328,53 @@ long long lb_batch_query(lb_batch *b, int key);
 int lb_batch_time_steps(lb_batch *b, int n, double *ms);
 int lb_batch_time_step_kernel(lb_batch *b, int n, double *ms);
 
+/* ---- two-dimensional D2Q9 lattices ---------------------------------------- */
+
+/*
+ * The paper's own model (Section 2: D2Q9, nine velocities; Section 3.3: the
+ * lid-driven cavity) run by the same fused pull update: BGK relaxation with
+ * the second-order equilibrium (Eq. 1-3), halfway bounce-back, periodic
+ * faces, FP32 storage of f - w, FP64 totals per step.
+ * Sites s = x + nx * y.  Populations (raw-state layout of lb2d_get_f):
+ *   0 (0,0); 1 (+1,0); 2 (-1,0); 3 (0,+1); 4 (0,-1); 5 (+1,+1); 6 (+1,-1);
+ *   7 (-1,+1); 8 (-1,-1).  Weights 4/9, 1/9, 1/36.
+ */
+typedef struct lb2d_lattice lb2d_lattice;
+
+/*
+ * Create an nx * ny lattice.  flags: HOST array of nx*ny bytes (copied) or
+ * NULL; 0 fluid, 1 wall (no-slip, at rest), 2 lid (a wall moving with
+ * velocity (lid_ux, lid_uy)): a population bounced off the lid gains
+ * 6 w_i (c_i . u_lid) (a moving wall of density 1).  tau > 0.5 or +INFINITY.
+ * hip_stream: borrowed, NULL = the default stream.  Starts at rest.
+ * Returns NULL on failure (lb_last_error()).
+ */
+lb2d_lattice *lb2d_create(int nx, int ny, double tau, const uint8_t *flags, double lid_ux, double lid_uy,
+                          void *hip_stream);
+void lb2d_destroy(lb2d_lattice *lat);
+
+/* Equilibrium initial state from caller-owned DEVICE FP64 rho (N) and u (2N, u_x then u_y); NULL = 1 / 0. */
+int lb2d_init_eq(lb2d_lattice *lat, const double *rho, const double *u);
+
+/* Enqueue n >= 0 steps. */
+int lb2d_step(lb2d_lattice *lat, int n);
+
+/* rho = sum f and u = sum c f / rho of the stored state into DEVICE rho (N) and u (2N); solid sites 0. */
+int lb2d_macros(lb2d_lattice *lat, float *rho, float *u);
+
+/* FP64 {mass, momentum x, y} of the fluid sites after each of the last k steps (out: 3k doubles). */
+int lb2d_sums(lb2d_lattice *lat, double *out, int k);
+
+/* Raw state: 9 planes of N floats (g = f - w), host or device (where). */
+int lb2d_get_f(lb2d_lattice *lat, void *buf, size_t bytes, int where);
+int lb2d_set_f(lb2d_lattice *lat, const void *buf, size_t bytes, int where);
+
+int lb2d_sync(lb2d_lattice *lat);
+long long lb2d_steps_done(lb2d_lattice *lat);
+
+/* Milliseconds for n steps between two HIP events on the lattice's stream (the state advances). */
+int lb2d_time_steps(lb2d_lattice *lat, int n, double *ms);
+
 #ifdef __cplusplus
 }
 #endif

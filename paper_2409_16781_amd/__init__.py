@@ -49,6 +49,17 @@ _SIGNATURES = {
     "lb_copy_probe": (ctypes.c_int, [_P, ctypes.c_int, _P]),
     "lb_set_force_field": (ctypes.c_int, [_P, _P]),
     "lb_grad_force_x": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _P]),
+    "lb2d_create": (_P, [ctypes.c_int, ctypes.c_int, ctypes.c_double, _P, ctypes.c_double, ctypes.c_double, _P]),
+    "lb2d_destroy": (None, [_P]),
+    "lb2d_init_eq": (ctypes.c_int, [_P, _P, _P]),
+    "lb2d_step": (ctypes.c_int, [_P, ctypes.c_int]),
+    "lb2d_macros": (ctypes.c_int, [_P, _P, _P]),
+    "lb2d_sums": (ctypes.c_int, [_P, _P, ctypes.c_int]),
+    "lb2d_get_f": (ctypes.c_int, [_P, _P, ctypes.c_size_t, ctypes.c_int]),
+    "lb2d_set_f": (ctypes.c_int, [_P, _P, ctypes.c_size_t, ctypes.c_int]),
+    "lb2d_sync": (ctypes.c_int, [_P]),
+    "lb2d_steps_done": (ctypes.c_longlong, [_P]),
+    "lb2d_time_steps": (ctypes.c_int, [_P, ctypes.c_int, _P]),
     "lb_batch_create": (_P, [ctypes.c_int, _P, _P, _P, ctypes.c_int, _P, ctypes.c_int]),
     "lb_batch_destroy": (None, [_P]),
     "lb_batch_set_force": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
@@ -268,6 +279,87 @@ class Lattice:
         _check(lib().lb_copy_probe(self._h, int(reps), ctypes.byref(ms)), "lb_copy_probe")
         return ms.value
 
+
+class Lattice2D:
+    """A two-dimensional D2Q9 lattice (the paper's own model); flags (ny, nx)
+    with 0 fluid, 1 wall, 2 lid moving with velocity ``lid``."""
+
+    def __init__(self, nx: int, ny: int, tau: float, flags=None, lid=(0.0, 0.0), stream=None):
+        import torch
+
+        self.nx, self.ny = int(nx), int(ny)
+        self.n = self.nx * self.ny
+        fl = None
+        if flags is not None:
+            fl = np.ascontiguousarray(flags, dtype=np.uint8)
+            if fl.shape != (self.ny, self.nx):
+                raise ValueError("flags must have shape (ny, nx)")
+        self._flags = fl
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        h = lib().lb2d_create(self.nx, self.ny, float(tau), None if fl is None else fl.ctypes.data_as(ctypes.c_void_p),
+                              float(lid[0]), float(lid[1]), ctypes.c_void_p(self._stream.cuda_stream))
+        if not h:
+            raise LBError(LB_EINVAL, "lb2d_create", last_error())
+        self._h = ctypes.c_void_p(h)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().lb2d_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init_eq(self, rho=None, u=None):
+        _check(lib().lb2d_init_eq(self._h, _ptr(rho), _ptr(u)), "lb2d_init_eq")
+
+    def step(self, n: int = 1):
+        _check(lib().lb2d_step(self._h, int(n)), "lb2d_step")
+
+    def macros(self):
+        import torch
+
+        rho = torch.empty((self.ny, self.nx), dtype=torch.float32, device="cuda")
+        u = torch.empty((2, self.ny, self.nx), dtype=torch.float32, device="cuda")
+        _check(lib().lb2d_macros(self._h, _ptr(rho), _ptr(u)), "lb2d_macros")
+        return rho, u
+
+    def sums(self, k: int = 1) -> np.ndarray:
+        out = np.zeros((k, 3), dtype=np.float64)
+        rc = lib().lb2d_sums(self._h, out.ctypes.data_as(ctypes.c_void_p), int(k))
+        if rc == LB_EUNSTABLE:
+            raise LBError(rc, "lb2d_sums", last_error())
+        _check(rc, "lb2d_sums")
+        return out
+
+    def get_f(self) -> np.ndarray:
+        out = np.empty((9, self.ny, self.nx), dtype=np.float32)
+        _check(lib().lb2d_get_f(self._h, out.ctypes.data_as(ctypes.c_void_p), out.nbytes, LB_HOST), "lb2d_get_f")
+        return out
+
+    def set_f(self, f: np.ndarray):
+        f = np.ascontiguousarray(f, dtype=np.float32)
+        if f.shape != (9, self.ny, self.nx):
+            raise ValueError("state must have shape (9, ny, nx)")
+        _check(lib().lb2d_set_f(self._h, f.ctypes.data_as(ctypes.c_void_p), f.nbytes, LB_HOST), "lb2d_set_f")
+
+    def sync(self):
+        _check(lib().lb2d_sync(self._h), "lb2d_sync")
+
+    @property
+    def steps_done(self) -> int:
+        return int(lib().lb2d_steps_done(self._h))
+
+    def time_steps(self, n: int) -> float:
+        ms = ctypes.c_double(0.0)
+        _check(lib().lb2d_time_steps(self._h, int(n), ctypes.byref(ms)), "lb2d_time_steps")
+        return ms.value
+
+
+WEIGHTS_D2Q9 = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
 
 C_X = np.array([0, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1, 0, 0, 0, 0])
 

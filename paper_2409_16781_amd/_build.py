@@ -9,7 +9,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblbm355.so")
-SOURCES = [os.path.join(CSRC, n) for n in ("lb_capi.hip", "lb_batch.hip", "lb_kernels.hip")]
+SOURCES = [os.path.join(CSRC, n) for n in ("lb_capi.hip", "lb_batch.hip", "lb_d2q9.hip", "lb_kernels.hip")]
 
 # -packed-fp32-ops: no packed FP32 instructions in device code (ordinary FP32
 # VALU only).  The host pass reports the feature as unknown; that is harmless.

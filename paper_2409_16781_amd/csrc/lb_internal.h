@@ -126,6 +126,24 @@ struct AdjArgs {
     float *grad;              // N floats (site order): += dJ/dF_x of this step
 };
 
+// One step of a two-dimensional D2Q9 lattice (FP32 storage of f - w).
+struct Step2Args {
+    const void *src;
+    void *dst;
+    Layout lay;               // rows are the ny lines of x (one block layout as in 3-D)
+    int nx, ny;
+    int nslots;               // ny * nx / sites per lane
+    int lds_edges, lg_row_lanes;
+    FastDiv div_pitch;
+    float hom;                // omega / 2
+    float ow1, ow2;           // omega w (axis 1/9, diagonal 1/36)
+    float q1, q2;             // (9/2) omega w
+    float lidc[9];            // 6 w_i (c_i . u_lid): added to a value bounced off the lid
+    const uint32_t *nbmask;   // bit i: site x - c_i solid; bit 8 + i: that site is the lid; bit 31: own solid
+    const uint8_t *rowdirty;  // per row: any mask bit set
+    double *partials;         // 4 doubles per workgroup (mass, px, py, 0)
+};
+
 // The reduction of one step's partials into the ring of per-step totals.
 struct TotalsArgs {
     const double *partials;   // 4 doubles per step workgroup
@@ -203,6 +221,15 @@ hipError_t launch_aa_planes(void *planes, void *state, const Layout &lay, int ny
 hipError_t launch_aa_step(int codec, int variant, bool solids, bool from_even, const StepArgs &a, int grid,
                           hipStream_t s);
 int aa_occupancy(int codec, int variant, bool solids, bool from_even);
+// D2Q9: variant 1 / 2 / 3 = 4 / 2 / 1 sites per lane (FP32 storage).
+hipError_t launch_step2d(int variant, bool solids, const Step2Args &a, int grid, hipStream_t s);
+hipError_t launch_masks2d(const uint8_t *flags, int nx, int ny, uint32_t *nbmask, uint8_t *rowdirty, hipStream_t s);
+hipError_t launch_init2d(void *dst, const Layout &lay, int nx, int ny, const double *rho, const double *u,
+                         const uint8_t *flags, hipStream_t s);
+hipError_t launch_macros2d(const void *src, const Layout &lay, int nx, int ny, const uint8_t *flags, float *rho,
+                           float *u, hipStream_t s);
+// Raw planes (9 x n floats, site order) to a D2Q9 array (to_state) or back.
+hipError_t launch_repack2d(void *planes, void *state, const Layout &lay, int64_t n, bool to_state, hipStream_t s);
 int sites_per_thread(int codec, int variant);
 
 }  // namespace lbm

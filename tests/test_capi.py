@@ -17,7 +17,7 @@ HEADER = os.path.join(ROOT, "include", "lb.h")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(lb_[a-z0-9_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(lb(?:2d)?_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_header_declares_the_boundary():
@@ -35,6 +35,34 @@ def test_library_exports_every_declared_symbol():
 
 def test_binding_signatures_cover_the_header():
     assert sorted(lbm._SIGNATURES) == declared_functions()
+    assert "lb2d_create" in declared_functions()
+
+
+@pytest.mark.parametrize("args,needle", [
+    ((0, 8, 0.8, None, 0.0, 0.0), "extents"),
+    ((8, 8, 0.5, None, 0.0, 0.0), "tau"),
+    ((8, 8, float("nan"), None, 0.0, 0.0), "tau"),
+    ((8, 8, 0.8, None, float("inf"), 0.0), "lid"),
+    ((1 << 16, 1 << 15, 0.8, None, 0.0, 0.0), "extents"),
+])
+def test_create2d_rejects_bad_arguments(args, needle):
+    h = lbm.lib().lb2d_create(*args, None)
+    assert not h
+    assert needle in lbm.last_error()
+
+
+def test_create2d_rejects_bad_flags():
+    flags = np.zeros((4, 4), dtype=np.uint8)
+    flags[1, 2] = 3
+    assert not lbm.lib().lb2d_create(4, 4, 0.8, flags.ctypes.data_as(ctypes.c_void_p), 0.0, 0.0, None)
+    assert "flag value 3" in lbm.last_error()
+
+
+def test_d2q9_calls_reject_null_handles():
+    L = lbm.lib()
+    assert L.lb2d_step(None, 1) == lbm.LB_ESTATE
+    assert L.lb2d_sync(None) == lbm.LB_ESTATE
+    L.lb2d_destroy(None)
 
 
 @pytest.mark.parametrize("args,needle", [

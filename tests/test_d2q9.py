@@ -1,0 +1,203 @@
+"""Two-dimensional D2Q9 lattices (the paper's own model and its lid-driven
+cavity workload) against the FP64 D2Q9 oracle (needs an MI355X).
+
+The GPU lattice stores f - w in FP32; its velocity field must match the
+oracle's to rel-L2 <= 1e-5 over the fluid sites, the same bar as the D3Q19
+FP32 path.  Pure streaming (omega = 0) is a permutation of the stored values
+and must match bit for bit.  Extents cover the three lane widths (4, 2 and 1
+sites per lane), rows that do and do not tile a workgroup, one-site rows and
+columns, and the paper's 4096^2 cavity for a few steps.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2409_16781_amd as lbm
+from paper_2409_16781_amd import inputs
+from gpu_util import require_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+TOL_U = 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _setup():
+    require_gpu()
+    oracle.build(force=False)
+
+
+def smooth(nx, ny, amp=0.05, seed=0):
+    """Seeded smooth rho and u on an (ny, nx) grid plus a little noise."""
+    rng = np.random.default_rng(seed)
+    y, x = np.meshgrid(np.arange(ny, dtype=np.float64), np.arange(nx, dtype=np.float64), indexing="ij")
+    kx, ky = 2 * math.pi / nx, 2 * math.pi / ny
+    rho = 1.0 + 0.01 * np.sin(kx * x) * np.cos(ky * y) + rng.uniform(-1e-4, 1e-4, (ny, nx))
+    u = np.stack([amp * np.sin(kx * x + 0.3) * np.cos(ky * y), -amp * np.cos(kx * x) * np.sin(ky * y + 0.7)])
+    return np.ascontiguousarray(rho), np.ascontiguousarray(u + rng.uniform(-1e-3, 1e-3, u.shape))
+
+
+def rel_l2(a, b, m):
+    return float(np.sqrt(((a - b)[:, m] ** 2).sum() / max((b[:, m] ** 2).sum(), 1e-300)))
+
+
+def run_pair(nx, ny, tau, steps, flags=None, lid=(0.0, 0.0), fields=True, seed=0, variant=None, monkeypatch=None):
+    torch = require_gpu()
+    if variant is not None:
+        monkeypatch.setenv("LB_KERNEL2D", str(variant))
+    rho, u = smooth(nx, ny, seed=seed) if fields else (None, None)
+    if rho is not None and flags is not None:
+        u[:, flags > 0] = 0.0
+    lat = lbm.Lattice2D(nx, ny, tau, flags=flags, lid=lid)
+    lat.init_eq(None if rho is None else torch.from_numpy(rho).cuda(), None if u is None else torch.from_numpy(u).cuda())
+    lat.step(steps)
+    r, v = lat.macros()
+    r, v = r.double().cpu().numpy(), v.double().cpu().numpy()
+    S = oracle.d2_run(oracle.d2_init((ny, nx), rho, u, flags), tau, steps, flags=flags, lid=lid)
+    r_ref, v_ref = oracle.d2_macros(S, flags=flags)
+    return lat, S, (r, v), (r_ref, v_ref)
+
+
+@pytest.mark.parametrize("nx,ny", [(64, 64), (61, 37), (62, 40), (96, 50), (1024, 24), (2048, 12), (256, 33)])
+def test_cavity_matches_oracle(nx, ny):
+    flags = inputs.cavity_flags(nx, ny)
+    say(f"[gpu] d2q9 cavity {nx}x{ny}, 200 steps")
+    lat, S, (r, v), (r_ref, v_ref) = run_pair(nx, ny, 0.6, 200, flags=flags, lid=(0.1, 0.0), seed=nx)
+    m = flags == 0
+    err = rel_l2(v, v_ref, m)
+    assert err <= TOL_U, err
+    assert np.abs(r - r_ref)[m].max() < 1e-5
+    assert np.all(r[~m] == 0.0) and np.all(v[:, ~m] == 0.0)
+    lat.close()
+
+
+@pytest.mark.parametrize("variant", [2, 3])
+def test_narrow_lane_widths_match_oracle(variant, monkeypatch):
+    flags = inputs.cavity_flags(64, 48)
+    say(f"[gpu] d2q9 cavity 64x48, lane width variant {variant}")
+    lat, _, (_, v), (_, v_ref) = run_pair(64, 48, 0.7, 150, flags=flags, lid=(0.08, 0.02), variant=variant,
+                                          monkeypatch=monkeypatch)
+    assert lat.nx == 64
+    assert rel_l2(v, v_ref, flags == 0) <= TOL_U
+    lat.close()
+
+
+@pytest.mark.parametrize("nx,ny", [(128, 48), (1, 9), (8, 1), (1, 1), (3, 5), (260, 7)])
+def test_periodic_box_matches_oracle(nx, ny):
+    say(f"[gpu] d2q9 periodic {nx}x{ny}")
+    lat, _, (r, v), (r_ref, v_ref) = run_pair(nx, ny, 0.8, 60, seed=7)
+    m = np.ones((ny, nx), bool)
+    assert rel_l2(v, v_ref, m) <= TOL_U
+    assert np.abs(r - r_ref).max() < 1e-5
+    lat.close()
+
+
+@pytest.mark.parametrize("nx,ny", [(64, 40), (61, 23), (1024, 10)])
+def test_pure_streaming_is_the_oracle_permutation(nx, ny):
+    """omega = 0, lid at rest: the update only moves stored values."""
+    flags = inputs.cavity_flags(nx, ny)
+    lat = lbm.Lattice2D(nx, ny, math.inf, flags=flags)
+    raw = np.random.default_rng(11).uniform(-0.02, 0.02, (9, ny, nx)).astype(np.float32)
+    say(f"[gpu] d2q9 pure streaming {nx}x{ny}")
+    lat.set_f(raw)
+    lat.step(5)
+    out = lat.get_f().astype(np.float64)
+    ref = oracle.d2_run(raw.astype(np.float64), math.inf, 5, flags=flags, lid=(0.0, 0.0))
+    m = flags == 0
+    assert np.array_equal(out[:, m], ref[:, m])
+    lat.close()
+
+
+def test_plane_couette_profile():
+    """Wall at y = 0, lid at y = ny - 1, periodic in x: steady u_x(y) = U (y - 1/2) / (ny - 2)."""
+    ny, U = 18, 0.05
+    flags = np.zeros((ny, 4), np.uint8)
+    flags[0] = 1
+    flags[-1] = 2
+    lat = lbm.Lattice2D(4, ny, 0.8, flags=flags, lid=(U, 0.0))
+    lat.init_eq()
+    say("[gpu] d2q9 Couette 4x18, 20000 steps")
+    lat.step(20000)
+    _, u = lat.macros()
+    u = u.double().cpu().numpy()
+    y = np.arange(1, ny - 1)
+    exact = U * (y - 0.5) / (ny - 2)
+    assert np.abs(u[0, 1:-1, :] - exact[:, None]).max() < 1e-6
+    assert np.abs(u[1, 1:-1, :]).max() < 1e-7
+    lat.close()
+
+
+def test_totals_follow_the_oracle_each_step():
+    nx = ny = 48
+    flags = inputs.cavity_flags(nx, ny)
+    lat = lbm.Lattice2D(nx, ny, 0.6, flags=flags, lid=(0.1, 0.0))
+    lat.init_eq()
+    S = oracle.d2_init((ny, nx), flags=flags)
+    say("[gpu] d2q9 totals 48x48")
+    lat.step(40)
+    got = lat.sums(40)
+    nf = float((flags == 0).sum())
+    for k in range(40):
+        S = oracle.d2_step(S, 0.6, flags=flags, lid=(0.1, 0.0))
+        ref = oracle.d2_sums(S, flags)
+        assert np.abs(got[k] - ref).max() <= 1e-6 * nf, (k, got[k], ref)
+    # mass is conserved by the cavity (the lid's momentum terms cancel)
+    assert np.abs(got[:, 0] - nf).max() <= 1e-7 * nf
+    lat.close()
+
+
+def test_state_roundtrip_and_errors():
+    lat = lbm.Lattice2D(40, 30, 0.7, flags=inputs.cavity_flags(40, 30), lid=(0.1, 0.0))
+    raw = np.random.default_rng(3).uniform(-0.1, 0.1, (9, 30, 40)).astype(np.float32)
+    say("[gpu] d2q9 state roundtrip")
+    lat.set_f(raw)
+    assert np.array_equal(lat.get_f(), raw)
+    lat.step(0)
+    assert np.array_equal(lat.get_f(), raw)
+    with pytest.raises(ValueError):
+        lat.set_f(raw[:, :-1])
+    with pytest.raises(lbm.LBError):
+        lat.sums(1)                       # no step taken yet
+    with pytest.raises(lbm.LBError):
+        lat.step(-1)
+    lat.close()
+
+
+def test_init_matches_oracle_equilibrium():
+    torch = require_gpu()
+    nx, ny = 33, 17
+    rho, u = smooth(nx, ny, seed=4)
+    lat = lbm.Lattice2D(nx, ny, 0.7)
+    say("[gpu] d2q9 init")
+    lat.init_eq(torch.from_numpy(rho).cuda(), torch.from_numpy(u).cuda())
+    g = lat.get_f().astype(np.float64)
+    _, w, _ = oracle.d2_lattice()
+    S = oracle.d2_init((ny, nx), rho, u)
+    assert np.abs(g + w[:, None, None] - S).max() < 1e-7
+    lat.close()
+
+
+def test_paper_cavity_4096_matches_oracle():
+    """The paper's workload: 4096^2 cavity, Re = 1e4, lid 0.1, from a
+    non-trivial state so that every site moves, a few steps."""
+    torch = require_gpu()
+    cfg = inputs.lid_cavity(4096)
+    ny, nx = cfg["shape"]
+    flags = cfg["flags"]
+    rho, u = smooth(nx, ny, amp=0.03, seed=9)
+    u[:, flags > 0] = 0.0
+    steps = 6
+    lat = lbm.Lattice2D(nx, ny, cfg["tau"], flags=flags, lid=cfg["lid"])
+    say(f"[gpu] d2q9 cavity 4096^2 tau {cfg['tau']:.5f}, {steps} steps")
+    lat.init_eq(torch.from_numpy(rho).cuda(), torch.from_numpy(u).cuda())
+    lat.step(steps)
+    _, v = lat.macros()
+    v = v.double().cpu().numpy()
+    S = oracle.d2_run(oracle.d2_init((ny, nx), rho, u, flags), cfg["tau"], steps, flags=flags, lid=cfg["lid"])
+    _, v_ref = oracle.d2_macros(S, flags=flags)
+    assert rel_l2(v, v_ref, flags == 0) <= TOL_U
+    sums = lat.sums(steps)
+    assert np.abs(sums[-1] - oracle.d2_sums(S, flags)).max() <= 1e-6 * float((flags == 0).sum())
+    lat.close()
