@@ -30,7 +30,7 @@ struct lb2d_lattice {
     int cur = 0;
     uint8_t *flags = nullptr;
     uint32_t *nbmask = nullptr;
-    uint8_t *rowdirty = nullptr;
+    uint8_t *chunkdirty = nullptr;  // one byte per 64 sites
     bool solids = false;
     double n_fluid = 0;
     double *partials = nullptr, *gpartials = nullptr, *ring = nullptr;
@@ -51,7 +51,7 @@ int check2(const lb2d_lattice *h)
 
 void release2(lb2d_lattice *h)
 {
-    void *p[] = {h->buf[0], h->buf[1], h->flags, h->nbmask, h->rowdirty, h->partials, h->gpartials, h->ring,
+    void *p[] = {h->buf[0], h->buf[1], h->flags, h->nbmask, h->chunkdirty, h->partials, h->gpartials, h->ring,
                  h->ticket, h->counter};
     for (void *q : p)
         if (q) (void)hipFree(q);
@@ -83,7 +83,7 @@ Step2Args step2_args(const lb2d_lattice *h, int from)
         a.lidc[i] = (float)(6.0 * w * (cx[i] * h->lid[0] + cy[i] * h->lid[1]));
     }
     a.nbmask = h->nbmask;
-    a.rowdirty = h->rowdirty;
+    a.chunkdirty = h->chunkdirty;
     a.partials = h->partials;
     return a;
 }
@@ -175,6 +175,8 @@ lb2d_lattice *lb2d_create(int nx, int ny, double tau, const uint8_t *flags, doub
     h->arr_elems = ((uint64_t)ny + R - 1) / R * h->lay.blk;
     const uint64_t tiles = (n / h->vsites + kBlock - 1) / kBlock;
     h->grid = (int)std::min<uint64_t>(tiles, 0x7fffffffull);
+    const long g = env_long("LB_GRID2D", 0);  // workgroups per launch (each loops over tiles), for sweeps
+    if (g >= 1 && (uint64_t)g < tiles) h->grid = (int)g;
 
     auto bail = [&](int code, const char *what, hipError_t e) -> lb2d_lattice * {
         release2(h);
@@ -200,10 +202,11 @@ lb2d_lattice *lb2d_create(int nx, int ny, double tau, const uint8_t *flags, doub
     if (h->solids) {
         if ((e = hipMalloc(&h->flags, n)) != hipSuccess) return bail(LB_ENOMEM, "hipMalloc(flags)", e);
         if ((e = hipMalloc(&h->nbmask, n * sizeof(uint32_t) + 64)) != hipSuccess) return bail(LB_ENOMEM, "hipMalloc(masks)", e);
-        if ((e = hipMalloc(&h->rowdirty, (size_t)ny)) != hipSuccess) return bail(LB_ENOMEM, "hipMalloc(rows)", e);
+        if ((e = hipMalloc(&h->chunkdirty, (size_t)(n + 63) / 64)) != hipSuccess)
+            return bail(LB_ENOMEM, "hipMalloc(chunks)", e);
         if ((e = hipMemcpyAsync(h->flags, flags, n, hipMemcpyHostToDevice, h->stream)) != hipSuccess)
             return bail(LB_EHIP, "flags upload", e);
-        if ((e = launch_masks2d(h->flags, nx, ny, h->nbmask, h->rowdirty, h->stream)) != hipSuccess)
+        if ((e = launch_masks2d(h->flags, nx, ny, h->nbmask, h->chunkdirty, h->stream)) != hipSuccess)
             return bail(LB_EHIP, "mask kernels", e);
     }
     if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return bail(LB_EHIP, "hipStreamSynchronize", e);

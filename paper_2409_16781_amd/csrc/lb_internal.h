@@ -64,7 +64,7 @@ struct Coll {
 
 Coll make_coll(float omega, float fx, float fy, float fz);
 
-constexpr int kRedChunk = 2048;  // step-workgroup partials summed by one reduce workgroup
+constexpr int kRedChunk = 256;   // step-workgroup partials summed by one reduce workgroup (one per thread)
 
 // Everything one step launch needs.  Pointers are device pointers.
 struct StepArgs {
@@ -140,7 +140,7 @@ struct Step2Args {
     float q1, q2;             // (9/2) omega w
     float lidc[9];            // 6 w_i (c_i . u_lid): added to a value bounced off the lid
     const uint32_t *nbmask;   // bit i: site x - c_i solid; bit 8 + i: that site is the lid; bit 31: own solid
-    const uint8_t *rowdirty;  // per row: any mask bit set
+    const uint8_t *chunkdirty;  // per 64 sites (site s in chunk s / 64): any mask bit set
     double *partials;         // 4 doubles per workgroup (mass, px, py, 0)
 };
 
@@ -223,7 +223,8 @@ hipError_t launch_aa_step(int codec, int variant, bool solids, bool from_even, c
 int aa_occupancy(int codec, int variant, bool solids, bool from_even);
 // D2Q9: variant 1 / 2 / 3 = 4 / 2 / 1 sites per lane (FP32 storage).
 hipError_t launch_step2d(int variant, bool solids, const Step2Args &a, int grid, hipStream_t s);
-hipError_t launch_masks2d(const uint8_t *flags, int nx, int ny, uint32_t *nbmask, uint8_t *rowdirty, hipStream_t s);
+// D2Q9 masks (nx * ny, site order) and one dirty byte per 64 sites ((n + 63) / 64 bytes).
+hipError_t launch_masks2d(const uint8_t *flags, int nx, int ny, uint32_t *nbmask, uint8_t *chunkdirty, hipStream_t s);
 hipError_t launch_init2d(void *dst, const Layout &lay, int nx, int ny, const double *rho, const double *u,
                          const uint8_t *flags, hipStream_t s);
 hipError_t launch_macros2d(const void *src, const Layout &lay, int nx, int ny, const uint8_t *flags, float *rho,

@@ -1535,9 +1535,26 @@ __global__ __launch_bounds__(kBlock) void step2d(Step2Args a)
 #pragma unroll
         for (int i = 0; i < kQ2; ++i)
             rb[i] = a.lay.row_base(CY2[i] > 0 ? ym : (CY2[i] < 0 ? yp : y)) + (uint64_t)i * a.lay.seg;
+        bool dirty = false;  // the V sites share one 64-site chunk (V | 64)
+        if constexpr (kSolids) dirty = a.chunkdirty[s0 >> 6] != 0;
         Lane<NW> d[kQ2];
 #pragma unroll
         for (int i = 0; i < kQ2; ++i) d[i] = ldv<NW>(src + (rb[i] + x0) * 4);
+        // Near solids: the masks and the site's own values of every population
+        // that may bounce, loaded together with the pulls (not after the
+        // masks).  Rows y +- 1 are not the own row, so directions 3..8 load
+        // their opposite at the own row; for 1 and 2 it is the unshifted pull.
+        uint32_t m[V];
+        Lane<NW> ownv[kQ2];
+        if constexpr (kSolids) {
+            if (dirty) {
+                load_masks<V>(a.nbmask + s0, m);
+#pragma unroll
+                for (int i = 3; i < kQ2; ++i) ownv[i] = ldv<NW>(src + (own + OPP2[i] * a.lay.seg) * 4);
+            }
+            ownv[1] = d[2];
+            ownv[2] = d[1];
+        }
 
         const bool left_edge = (lane == 0) || (x0 == 0);
         const bool row_end = x0 + V >= nx;
@@ -1586,24 +1603,15 @@ __global__ __launch_bounds__(kBlock) void step2d(Step2Args a)
 #pragma unroll
         for (int i = 0; i < kQ2; ++i) lidsel[i] = 0;
         if constexpr (kSolids) {
-            if (a.rowdirty[y]) {
-                uint32_t m[V];
-                load_masks<V>(a.nbmask + s0, m);
+            if (dirty) {
 #pragma unroll
                 for (int e = 0; e < V; ++e) dead |= (m[e] >> 31) << e;
 #pragma unroll
                 for (int i = 1; i < kQ2; ++i) {
-                    uint32_t sel = 0;
 #pragma unroll
                     for (int e = 0; e < V; ++e) {
-                        sel |= ((m[e] >> i) & 1u) << e;
+                        if ((m[e] >> i) & 1u) d[i].w[e] = ownv[i].w[e];
                         lidsel[i] |= ((m[e] >> (8 + i)) & 1u) << e;
-                    }
-                    if (sel) {
-                        const Lane<NW> o = ldv<NW>(src + (own + OPP2[i] * a.lay.seg) * 4);
-#pragma unroll
-                        for (int e = 0; e < V; ++e)
-                            if ((sel >> e) & 1u) d[i].w[e] = o.w[e];
                     }
                 }
             }
@@ -1828,6 +1836,18 @@ __global__ __launch_bounds__(kBlock) void build_rowdirty(const uint32_t *nbmask,
         uint32_t any = 0;
         for (int x = 0; x < pitch; ++x) any |= nbmask[(size_t)r * pitch + x];
         rowdirty[r] = any ? 1 : 0;
+    }
+}
+
+// One byte per 64 consecutive sites: 1 if any of them has a mask bit set.
+__global__ __launch_bounds__(kBlock) void build_chunkdirty(const uint32_t *nbmask, int64_t n, uint8_t *dirty)
+{
+    const int64_t nchunks = (n + 63) / 64;
+    for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < nchunks; c += (int64_t)gridDim.x * kBlock) {
+        const int64_t end = (c + 1) * 64 < n ? (c + 1) * 64 : n;
+        uint32_t any = 0;
+        for (int64_t s = c * 64; s < end; ++s) any |= nbmask[s];
+        dirty[c] = any ? 1 : 0;
     }
 }
 
@@ -2110,10 +2130,11 @@ hipError_t launch_step2d(int variant, bool solids, const Step2Args &a, int grid,
     return hipLaunchKernel(fn, dim3(grid), dim3(kBlock), params, 0, s);
 }
 
-hipError_t launch_masks2d(const uint8_t *flags, int nx, int ny, uint32_t *nbmask, uint8_t *rowdirty, hipStream_t s)
+hipError_t launch_masks2d(const uint8_t *flags, int nx, int ny, uint32_t *nbmask, uint8_t *chunkdirty, hipStream_t s)
 {
-    build_masks2d<<<grid_for((uint64_t)nx * ny), kBlock, 0, s>>>(flags, nx, ny, nbmask);
-    build_rowdirty<<<grid_for((uint64_t)ny), kBlock, 0, s>>>(nbmask, nx, ny, rowdirty);
+    const int64_t n = (int64_t)nx * ny;
+    build_masks2d<<<grid_for((uint64_t)n), kBlock, 0, s>>>(flags, nx, ny, nbmask);
+    build_chunkdirty<<<grid_for((uint64_t)(n + 63) / 64), kBlock, 0, s>>>(nbmask, n, chunkdirty);
     return hipGetLastError();
 }
 

@@ -60,7 +60,8 @@ def run_pair(nx, ny, tau, steps, flags=None, lid=(0.0, 0.0), fields=True, seed=0
     return lat, S, (r, v), (r_ref, v_ref)
 
 
-@pytest.mark.parametrize("nx,ny", [(64, 64), (61, 37), (62, 40), (96, 50), (1024, 24), (2048, 12), (256, 33)])
+@pytest.mark.parametrize("nx,ny", [(64, 64), (61, 37), (62, 40), (96, 50), (1024, 24), (2048, 12), (256, 33),
+                                   (1000, 70)])
 def test_cavity_matches_oracle(nx, ny):
     flags = inputs.cavity_flags(nx, ny)
     say(f"[gpu] d2q9 cavity {nx}x{ny}, 200 steps")
@@ -70,7 +71,45 @@ def test_cavity_matches_oracle(nx, ny):
     assert err <= TOL_U, err
     assert np.abs(r - r_ref)[m].max() < 1e-5
     assert np.all(r[~m] == 0.0) and np.all(v[:, ~m] == 0.0)
+    # FP64 totals of the last step (reduced inside the step launch)
+    assert np.abs(lat.sums(1)[0] - oracle.d2_sums(S, flags)).max() <= 1e-6 * float(m.sum())
     lat.close()
+
+
+@pytest.mark.parametrize("grid", [1, 5, 66])
+def test_fewer_workgroups_than_tiles(grid, monkeypatch):
+    """Workgroups looping over several tiles (and group sizes of the in-launch
+    totals reduction that do not divide the grid) give the same state bit for
+    bit, and the same totals up to the order of the FP64 sums."""
+    flags = inputs.cavity_flags(1000, 70)    # 69 tiles of 256 lanes
+    outs = []
+    for g in (None, grid):
+        if g is None:
+            monkeypatch.delenv("LB_GRID2D", raising=False)
+        else:
+            monkeypatch.setenv("LB_GRID2D", str(g))
+        lat = lbm.Lattice2D(1000, 70, 0.6, flags=flags, lid=(0.1, 0.0))
+        lat.init_eq()
+        say(f"[gpu] d2q9 cavity 1000x70, grid {g}")
+        lat.step(30)
+        outs.append((lat.get_f(), lat.sums(30)))
+        lat.close()
+    m = flags == 0
+    assert np.array_equal(outs[0][0][:, m], outs[1][0][:, m])
+    assert np.allclose(outs[0][1], outs[1][1], rtol=0, atol=1e-12 * m.sum())
+
+
+def test_totals_are_reproducible():
+    flags = inputs.cavity_flags(512, 300)
+    got = []
+    for _ in range(2):
+        lat = lbm.Lattice2D(512, 300, 0.6, flags=flags, lid=(0.1, 0.0))
+        lat.init_eq()
+        say("[gpu] d2q9 cavity 512x300 totals twice")
+        lat.step(25)
+        got.append(lat.sums(25))
+        lat.close()
+    assert np.array_equal(got[0], got[1])
 
 
 @pytest.mark.parametrize("variant", [2, 3])
