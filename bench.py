@@ -55,18 +55,28 @@ def workload_fields(n):
     return cfg
 
 
+STEP_KERNEL_SOURCES = ("lb_internal.h", "lb_device.h", "lb_kernels.hip")
+
+
+def step_kernel_digest(root):
+    """SHA-256 over the sources the single-lattice step kernel is built from."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in STEP_KERNEL_SOURCES:
+        h.update(open(os.path.join(root, "paper_2409_16781_amd", "csrc", name), "rb").read())
+    return h.hexdigest()
+
+
 def measured_traffic(codec, n):
     """HBM bytes per step-kernel launch from the committed rocprofv3 counters
     (FETCH_SIZE and WRITE_SIZE, each scaled by what it reads for a copy of
     known size), or None when the kernel source changed since they were taken
     or the lattice differs."""
-    import hashlib
     here = os.path.dirname(os.path.abspath(__file__))
     path = os.path.join(here, "profiles", "step_vec_512cube_tgv.traffic.json")
-    src = os.path.join(here, "paper_2409_16781_amd", "csrc", "lb_kernels.hip")
     try:
         tr = json.load(open(path))
-        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        digest = step_kernel_digest(here)
     except OSError:
         return None
     if n != 512 or tr.get("kernel_source_sha256") != digest:

@@ -1,0 +1,161 @@
+// The adjoint (reverse-mode derivative) of the fused D3Q19 step.
+#include "lb_device.h"
+
+namespace lbm {
+namespace {
+
+// ------------------------------------------------------------ adjoint --
+// Reverse-mode derivative of one step (FP32 storage).  A step maps the
+// stored state S_n to S_{n+1} = C(P S_n): P is the pull streaming with
+// bounce-back, C the per-site BGK collision with Guo forcing (Eq. 1-3).  For
+// an objective J(S_N) the adjoint lam_n = dJ/dS_n obeys lam_n = P^T nu_n with
+// nu_n = (dC/df)^T lam_{n+1} at every site, where f = P S_n.  The kernel of
+// step n gathers lam_{n+1} = P^T nu_{n+1} (the transposed pull of the
+// previous adjoint array; for the last step lam_N is read at the site
+// itself), gathers f from S_n, and writes nu_n.  With rho, u the moments of f
+// (u with the half-force shift), w_i the weights and F the site's force:
+//   nu_j = (1 - omega) lam_j + A + B.(c_j - u) / rho
+//   A    = omega sum_i lam_i w_i (1 + 3 c_i.u + 9/2 (c_i.u)^2 - 3/2 u.u)
+//   B    = sum_i lam_i w_i c_i [3 omega rho + 9 omega rho c_i.u + 9 (1 - omega/2) c_i.F]
+//          - 3 (omega rho u + (1 - omega/2) F) sum_i lam_i w_i
+// (A and B are lam contracted with dfeq/drho and with dfeq/du + dS/du), and
+// the x-force of the site receives
+//   dJ/dF_x += B_x / (2 rho) + (1 - omega/2)(3 sum_i lam_i w_i c_ix
+//              - 3 u_x sum_i lam_i w_i + 9 sum_i lam_i w_i (c_i.u) c_ix).
+// Solid sites keep nu = 0 and no gradient.
+
+template <int NW, bool kFirst, bool kSolids>
+__global__ __launch_bounds__(kBlock) void adjoint_vec(AdjArgs a)
+{
+    using K = Codec<kF32>;
+    constexpr int V = NW;
+    __shared__ EdgeLds lds;
+    const StepArgs &sa = a.s;
+    const Coll &cp = sa.coll;
+    const float om = 2.0f * cp.hom;        // omega
+    const float k1 = 1.0f - cp.hom;        // 1 - omega/2
+    const char *state = reinterpret_cast<const char *>(a.state);
+    const char *lam_src = reinterpret_cast<const char *>(a.lam_in);
+    char *nu_out = reinterpret_cast<char *>(a.nu_out);
+    const int ntiles = (sa.nslots + kBlock - 1) / kBlock;
+    for (int b = blockIdx.x; b < ntiles; b += gridDim.x) {
+        const TileGeom g = tile_geom<V, false>(sa, b);
+        Lane<NW> d[kQ];
+        const uint32_t dead = gather<kF32, NW, kSolids, false, false>(sa, state, g, d, lds);
+        // moments of the pulled pre-collision populations (shifted storage)
+        float rho[V], ux[V], uy[V], uz[V], fx[V];
+        float fxf[V];
+        if (sa.fx_field)
+            load_masks<V>(reinterpret_cast<const uint32_t *>(sa.fx_field) + g.s0, reinterpret_cast<uint32_t(&)[V]>(fxf));
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            float gg[kQ];
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) gg[i] = K::dec(d[i].w[e]);
+            float dr = 0.0f, jx = 0.0f, jy = 0.0f, jz = 0.0f;
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) {
+                dr += gg[i];
+                if (CX[i]) jx += CX[i] * gg[i];
+                if (CY[i]) jy += CY[i] * gg[i];
+                if (CZ[i]) jz += CZ[i] * gg[i];
+            }
+            fx[e] = cp.fx + (sa.fx_field ? fxf[e] : 0.0f);
+            rho[e] = 1.0f + dr;
+            const float inv = 1.0f / rho[e];
+            ux[e] = (jx + 0.5f * fx[e]) * inv;
+            uy[e] = (jy + cp.hfy) * inv;
+            uz[e] = (jz + cp.hfz) * inv;
+        }
+        // adjoint of the next state at this step's sites
+        if constexpr (kFirst) {
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) d[i] = ldv<NW>(lam_src + (g.own + i * sa.lay.seg) * K::kBytes);
+        } else {
+            (void)gather<kF32, NW, kSolids, false, true>(sa, lam_src, g, d, lds);
+        }
+        float gF[V];
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            float lam[kQ];
+#pragma unroll
+            for (int k = 0; k < kQ; ++k) lam[k] = K::dec(kFirst ? d[k].w[e] : d[OPP[k]].w[e]);
+            const float r = rho[e], u0 = ux[e], u1 = uy[e], u2 = uz[e];
+            const float uu = u0 * u0 + u1 * u1 + u2 * u2;
+            const float F0 = fx[e], F1 = cp.fy, F2 = cp.fz;
+            const float orr = om * r;
+            float Lw = 0.0f, A = 0.0f, B0 = 0.0f, B1 = 0.0f, B2 = 0.0f, G0 = 0.0f, H0 = 0.0f;
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) {
+                const float w = weight_class(i) == 0 ? 1.0f / 3.0f : (weight_class(i) == 1 ? W1 : W2);
+                const float lw = lam[i] * w;
+                const float cu = CX[i] * u0 + CY[i] * u1 + CZ[i] * u2;
+                const float cF = CX[i] * F0 + CY[i] * F1 + CZ[i] * F2;
+                Lw += lw;
+                A += lw * (1.0f + 3.0f * cu + 4.5f * cu * cu - 1.5f * uu);
+                const float t = lw * (3.0f * orr + 9.0f * orr * cu + 9.0f * k1 * cF);
+                if (CX[i]) {
+                    B0 += CX[i] * t;
+                    G0 += CX[i] * lw;
+                    H0 += CX[i] * lw * cu;
+                }
+                if (CY[i]) B1 += CY[i] * t;
+                if (CZ[i]) B2 += CZ[i] * t;
+            }
+            A *= om;
+            B0 -= 3.0f * (orr * u0 + k1 * F0) * Lw;
+            B1 -= 3.0f * (orr * u1 + k1 * F1) * Lw;
+            B2 -= 3.0f * (orr * u2 + k1 * F2) * Lw;
+            const float inv = 1.0f / r;
+            gF[e] = 0.5f * B0 * inv + k1 * (3.0f * G0 - 3.0f * u0 * Lw + 9.0f * H0);
+            const float base = A - (B0 * u0 + B1 * u1 + B2 * u2) * inv;
+#pragma unroll
+            for (int j = 0; j < kQ; ++j) {
+                const float cB = CX[j] * B0 + CY[j] * B1 + CZ[j] * B2;
+                const float nu = (1.0f - om) * lam[j] + base + cB * inv;
+                d[j].w[e] = K::enc((dead >> e) & 1u ? 0.0f : nu);
+            }
+        }
+        if (g.active) {
+            if (dead != (1u << V) - 1u) {
+                const StoreBase sb = store_base(nu_out, g.own, K::kBytes);
+#pragma unroll
+                for (int i = 0; i < kQ; ++i) stv_at<NW>(nu_out, sb, g.own + i * sa.lay.seg, K::kBytes, d[i]);
+                float gr[V];
+                load_masks<V>(reinterpret_cast<const uint32_t *>(a.grad) + g.s0, reinterpret_cast<uint32_t(&)[V]>(gr));
+#pragma unroll
+                for (int e = 0; e < V; ++e)
+                    if (!((dead >> e) & 1u)) gr[e] += gF[e];
+                store_floats<V>(a.grad + g.s0, gr);
+            }
+        }
+    }
+}
+
+}  // namespace
+
+namespace {
+template <int NW, bool S>
+void *adjoint_fn(bool first)
+{
+    return first ? reinterpret_cast<void *>(&adjoint_vec<NW, true, S>) : reinterpret_cast<void *>(&adjoint_vec<NW, false, S>);
+}
+template <bool S>
+void *pick_adjoint(int variant, bool first)
+{
+    if (variant == 1) return adjoint_fn<4, S>(first);
+    if (variant == 2) return adjoint_fn<2, S>(first);
+    return adjoint_fn<1, S>(first);
+}
+}  // namespace
+
+hipError_t launch_adjoint(int variant, bool first, const AdjArgs &a, int grid, hipStream_t s)
+{
+    const bool solids = a.s.nbmask != nullptr;
+    void *fn = solids ? pick_adjoint<true>(variant, first) : pick_adjoint<false>(variant, first);
+    AdjArgs arg = a;
+    void *params[] = {&arg};
+    return hipLaunchKernel(fn, dim3(grid), dim3(kBlock), params, 0, s);
+}
+
+}  // namespace lbm
