@@ -56,14 +56,18 @@ struct Lane {
 #define LB_NT_STORE 1
 #endif
 
-template <typename T>
+// kNT = false: an ordinary (cached) load.  Kernels with solid sites pull
+// with cached loads: a bounce-back load of a site's own opposite population
+// then tends to hit the L2 line that the tile pulling that population from
+// the site's row has just fetched, instead of fetching a whole line for one
+// lane's element again.
+template <typename T, bool kNT = true>
 __device__ __forceinline__ T ldg(const T *p)
 {
 #if LB_NT_LOAD
-    return __builtin_nontemporal_load(p);
-#else
-    return *p;
+    if constexpr (kNT) return __builtin_nontemporal_load(p);
 #endif
+    return *p;
 }
 
 template <typename T>
@@ -76,22 +80,22 @@ __device__ __forceinline__ void stg(T *p, T v)
 #endif
 }
 
-template <int NW>
+template <int NW, bool kNT = true>
 __device__ __forceinline__ Lane<NW> ldv(const char *p)
 {
     Lane<NW> r;
     if constexpr (NW == 4) {
-        const u32x4 v = ldg(reinterpret_cast<const u32x4 *>(p));
+        const u32x4 v = ldg<u32x4, kNT>(reinterpret_cast<const u32x4 *>(p));
         r.w[0] = v[0];
         r.w[1] = v[1];
         r.w[2] = v[2];
         r.w[3] = v[3];
     } else if constexpr (NW == 2) {
-        const u32x2 v = ldg(reinterpret_cast<const u32x2 *>(p));
+        const u32x2 v = ldg<u32x2, kNT>(reinterpret_cast<const u32x2 *>(p));
         r.w[0] = v[0];
         r.w[1] = v[1];
     } else {
-        r.w[0] = ldg(reinterpret_cast<const uint32_t *>(p));
+        r.w[0] = ldg<uint32_t, kNT>(reinterpret_cast<const uint32_t *>(p));
     }
     return r;
 }
@@ -632,7 +636,7 @@ __device__ __forceinline__ uint32_t gather(const StepArgs &a, const char *src, c
         rb[i] = a.lay.row_base(zs * ny + ys) + (uint64_t)(kSwap ? OPP[i] : i) * a.lay.seg;
     }
 #pragma unroll
-    for (int i = 0; i < kQ; ++i) d[i] = ldv<NW>(src + (rb[i] + x0) * K::kBytes);
+    for (int i = 0; i < kQ; ++i) d[i] = ldv<NW, !kSolids>(src + (rb[i] + x0) * K::kBytes);
 
     // +-1 shifts along x (all lanes take part in the DPP moves).  The element
     // a lane needs from beyond its wave or across the periodic wrap comes
