@@ -335,12 +335,25 @@ class Lattice2D:
         _check(rc, "lb2d_sums")
         return out
 
-    def get_f(self) -> np.ndarray:
+    def get_f(self, device: bool = False):
+        """Raw state g = f - w as (9, ny, nx) float32: numpy, or a CUDA tensor with device=True."""
+        if device:
+            import torch
+
+            out = torch.empty((9, self.ny, self.nx), dtype=torch.float32, device="cuda")
+            _check(lib().lb2d_get_f(self._h, _ptr(out), out.numel() * 4, LB_DEVICE), "lb2d_get_f")
+            return out
         out = np.empty((9, self.ny, self.nx), dtype=np.float32)
         _check(lib().lb2d_get_f(self._h, out.ctypes.data_as(ctypes.c_void_p), out.nbytes, LB_HOST), "lb2d_get_f")
         return out
 
-    def set_f(self, f: np.ndarray):
+    def set_f(self, f):
+        """Set the raw state from a (9, ny, nx) float32 numpy array or CUDA tensor."""
+        if hasattr(f, "is_cuda") and f.is_cuda:
+            if tuple(f.shape) != (9, self.ny, self.nx) or str(f.dtype) != "torch.float32" or not f.is_contiguous():
+                raise ValueError("state must be a contiguous float32 tensor of shape (9, ny, nx)")
+            _check(lib().lb2d_set_f(self._h, _ptr(f), f.numel() * 4, LB_DEVICE), "lb2d_set_f")
+            return
         f = np.ascontiguousarray(f, dtype=np.float32)
         if f.shape != (9, self.ny, self.nx):
             raise ValueError("state must have shape (9, ny, nx)")

@@ -240,3 +240,44 @@ def test_paper_cavity_4096_matches_oracle():
     sums = lat.sums(steps)
     assert np.abs(sums[-1] - oracle.d2_sums(S, flags)).max() <= 1e-6 * float((flags == 0).sum())
     lat.close()
+
+
+def test_cavity_16384_sampled_light_cones():
+    """A 16384^2 cavity (2.4e9 stored elements per array, past 32-bit
+    element indices) from a random state, 4 steps; at sampled sites the GPU
+    fields must equal the oracle run on the 11 x 11 window around the site
+    (after 4 steps a site depends only on sites within 4 of it)."""
+    torch = require_gpu()
+    n, steps, tau, lid = 16384, 4, 0.6, (0.1, 0.0)
+    flags = inputs.cavity_flags(n, n)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(5)
+    planes = torch.rand((9, n, n), generator=gen, dtype=torch.float32, device="cuda") * 0.02 - 0.01
+    samples = [(1, 1), (2, n - 2), (n // 2, n - 2), (n - 2, n - 2), (n - 2, 1), (n // 2, n // 2), (12345, 16001),
+               (3, 8000), (16380, 9000), (7777, 2)]
+    h = steps + 1
+    idx = np.arange(-h, h + 1)
+    windows = []
+    for x, y in samples:
+        ys, xs = (y + idx) % n, (x + idx) % n
+        win = planes[:, torch.from_numpy(ys).cuda()][:, :, torch.from_numpy(xs).cuda()].double().cpu().numpy()
+        windows.append((win, flags[np.ix_(ys, xs)]))
+    lat = lbm.Lattice2D(n, n, tau, flags=flags, lid=lid)
+    say(f"[gpu] d2q9 cavity {n}^2 random state, {steps} steps, {len(samples)} light-cone samples")
+    lat.set_f(planes)
+    del planes
+    torch.cuda.empty_cache()
+    lat.step(steps)
+    rho, u = lat.macros()
+    sy = torch.tensor([y for _, y in samples], device="cuda")
+    sx = torch.tensor([x for x, _ in samples], device="cuda")
+    r_gpu = rho[sy, sx].double().cpu().numpy()
+    u_gpu = u[:, sy, sx].double().cpu().numpy()
+    del rho, u
+    lat.close()
+    _, w, _ = oracle.d2_lattice()
+    for k, ((win, fl), (x, y)) in enumerate(zip(windows, samples)):
+        S = oracle.d2_run(win + w[:, None, None], tau, steps, flags=fl, lid=lid)
+        r_ref, u_ref = oracle.d2_macros(S, flags=fl)
+        assert abs(r_gpu[k] - r_ref[h, h]) < 1e-6, (x, y)
+        assert np.abs(u_gpu[:, k] - u_ref[:, h, h]).max() < 2e-7, (x, y, u_gpu[:, k], u_ref[:, h, h])
