@@ -59,11 +59,16 @@ STEP_KERNEL_SOURCES = ("lb_internal.h", "lb_device.h", "lb_kernels.hip")
 
 
 def step_kernel_digest(root):
-    """SHA-256 over the sources the single-lattice step kernel is built from."""
+    """SHA-256 over the code (comments and whitespace removed) of the sources
+    the single-lattice step kernel is built from."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for name in STEP_KERNEL_SOURCES:
-        h.update(open(os.path.join(root, "paper_2409_16781_amd", "csrc", name), "rb").read())
+        text = open(os.path.join(root, "paper_2409_16781_amd", "csrc", name)).read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()
 
 

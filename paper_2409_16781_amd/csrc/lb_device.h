@@ -17,7 +17,7 @@
 // gives the density deviation rho - 1 and, because sum_i w_i c_i = 0, the
 // momentum directly.
 //
-// The update is bound by HBM bandwidth (Section 5.3 finds the paper's kernel
+// The update is bound by HBM bandwidth (Section 5.4 finds the paper's kernel
 // memory-bound on every device), so the kernels are built around the memory
 // stream: 8- or 16-byte loads and stores per lane and population, lanes along
 // x, the +-1 x-shift of the pulled rows exchanged between neighbouring lanes
