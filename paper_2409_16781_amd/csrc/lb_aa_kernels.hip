@@ -142,8 +142,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(vec_wave
 // Even -> odd: gather (transposed slots), collide, push to the neighbours.
 // (The 16-bit codecs keep the three-wave budget of the two-array step: with
 // two waves and no spills the kernel measured 10% slower at 512^3.)
+// Wave budget of the push step: the FP16 push spills at three waves per SIMD
+// (168 VGPRs) and runs faster at two (2.33 against 2.59 ms per 512^3 step);
+// BF16 spills less and keeps three (1.83 ms).
+template <int C, int NW>
+constexpr int push_waves()
+{
+    return (C == kF16 && NW <= 2) ? 2 : vec_waves<C, NW>();
+}
+
 template <int C, int NW, bool kSolids>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(vec_waves<C, NW>()))) void aa_pullpush(StepArgs a)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(push_waves<C, NW>()))) void aa_pullpush(StepArgs a)
 {
     using K = Codec<C>;
     constexpr int V = NW * 4 / K::kBytes;
