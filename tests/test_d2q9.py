@@ -281,3 +281,37 @@ def test_cavity_16384_sampled_light_cones():
         r_ref, u_ref = oracle.d2_macros(S, flags=fl)
         assert abs(r_gpu[k] - r_ref[h, h]) < 1e-6, (x, y)
         assert np.abs(u_gpu[:, k] - u_ref[:, h, h]).max() < 2e-7, (x, y, u_gpu[:, k], u_ref[:, h, h])
+
+
+def test_paper_cavity_full_length_properties():
+    """The paper's run length (4096^2, Re = 1e4, 100,000 steps): no oracle at
+    that size, so properties that hold at any size: finite fields and totals,
+    mass kept to FP32 storage rounding, speeds bounded by the lid's, the flow
+    dragged along +x under the lid, and a return flow along the vertical
+    centre line.  (After 100,000 steps the flow has run only ~2.4 lid transit
+    times and is weakly compressible, Mach 0.17: the net flux through the
+    centre line is still ~10% of the gross flux, so it is not tested.)"""
+    torch = require_gpu()
+    cfg = inputs.lid_cavity(4096)
+    ny, nx = cfg["shape"]
+    u0 = cfg["lid"][0]
+    lat = lbm.Lattice2D(nx, ny, cfg["tau"], flags=cfg["flags"], lid=cfg["lid"])
+    lat.init_eq()
+    steps = 100_000
+    say(f"[gpu] d2q9 cavity 4096^2, {steps} steps (the paper's run length)")
+    for _ in range(10):
+        lat.step(steps // 10)
+        lat.sync()
+    assert lat.steps_done == steps
+    sums = lat.sums(1000)
+    nf = float((cfg["flags"] == 0).sum())
+    assert np.all(np.isfinite(sums))
+    assert np.abs(sums[:, 0] - nf).max() <= 1e-7 * nf
+    rho, u = lat.macros()
+    u = u.double()
+    assert bool(torch.isfinite(u).all())
+    assert float(torch.sqrt(u[0] ** 2 + u[1] ** 2).max()) <= 1.2 * u0
+    jx = (rho.double() * u[0])[1:ny - 1, nx // 2].cpu().numpy()   # fluid rows of the centre column
+    assert jx[-1] > 0.3 * u0                                      # dragged by the lid
+    assert jx.min() < 0.0                                         # return flow
+    lat.close()
