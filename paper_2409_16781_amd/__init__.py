@@ -314,6 +314,13 @@ class Lattice2D:
             pass
 
     def init_eq(self, rho=None, u=None):
+        """rho (ny, nx), u (2, ny, nx): float64 CUDA tensors (or None)."""
+        import torch
+
+        for t, shape in ((rho, (self.ny, self.nx)), (u, (2, self.ny, self.nx))):
+            if t is not None and (tuple(t.shape) != shape or t.dtype != torch.float64 or not t.is_cuda
+                                  or not t.is_contiguous()):
+                raise ValueError(f"expected a contiguous float64 CUDA tensor of shape {shape}")
         _check(lib().lb2d_init_eq(self._h, _ptr(rho), _ptr(u)), "lb2d_init_eq")
 
     def step(self, n: int = 1):

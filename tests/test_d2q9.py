@@ -315,3 +315,15 @@ def test_paper_cavity_full_length_properties():
     assert jx[-1] > 0.3 * u0                                      # dragged by the lid
     assert jx.min() < 0.0                                         # return flow
     lat.close()
+
+
+def test_init_rejects_bad_tensors():
+    torch = require_gpu()
+    lat = lbm.Lattice2D(16, 8, 0.7)
+    with pytest.raises(ValueError):
+        lat.init_eq(torch.ones((8, 16), dtype=torch.float32, device="cuda"))
+    with pytest.raises(ValueError):
+        lat.init_eq(None, torch.zeros((3, 8, 16), dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError):
+        lat.init_eq(torch.ones((8, 16), dtype=torch.float64))          # host tensor
+    lat.close()
