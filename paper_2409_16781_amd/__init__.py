@@ -218,9 +218,15 @@ class Lattice:
         _check(lib().lb_set_f(self._h, f.ctypes.data_as(ctypes.c_void_p), f.nbytes, LB_HOST), "lb_set_f")
 
     def get_f_device(self, out):
+        """Raw state into a contiguous CUDA tensor of 19 * N storage elements."""
+        if not (out.is_cuda and out.is_contiguous()):
+            raise ValueError("expected a contiguous CUDA tensor")
         _check(lib().lb_get_f(self._h, _ptr(out), out.numel() * out.element_size(), LB_DEVICE), "lb_get_f")
 
     def set_f_device(self, f):
+        """Raw state from a contiguous CUDA tensor of 19 * N storage elements."""
+        if not (f.is_cuda and f.is_contiguous()):
+            raise ValueError("expected a contiguous CUDA tensor")
         _check(lib().lb_set_f(self._h, _ptr(f), f.numel() * f.element_size(), LB_DEVICE), "lb_set_f")
 
     def sync(self):
