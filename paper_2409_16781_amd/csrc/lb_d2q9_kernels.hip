@@ -96,11 +96,15 @@ __global__ __launch_bounds__(kBlock) void step2d(Step2Args a)
             ownv[2] = d[1];
         }
 
+        // x-edges: the element beyond a wave comes from the neighbouring
+        // wave through LDS when that wave is in this tile and the element is
+        // in the same row; the periodic wrap too when tiles hold whole rows;
+        // anything else (tile ends of long rows) by a direct load
         const bool left_edge = (lane == 0) || (x0 == 0);
         const bool row_end = x0 + V >= nx;
         const bool right_edge = (lane == 63) || row_end;
+        __syncthreads();  // the previous tile's readers of lds are done
         if (a.lds_edges) {
-            __syncthreads();
             if (row_end) {
 #pragma unroll
                 for (int k = 0; k < 3; ++k) lds.row_last[rit][k] = d[kPlusX2[k]].w[NW - 1];
@@ -109,32 +113,35 @@ __global__ __launch_bounds__(kBlock) void step2d(Step2Args a)
 #pragma unroll
                 for (int k = 0; k < 3; ++k) lds.row_first[rit][k] = d[kMinusX2[k]].w[0];
             }
-            if (lane == 63) {
-#pragma unroll
-                for (int k = 0; k < 3; ++k) lds.wave_last[wave][k] = d[kPlusX2[k]].w[NW - 1];
-            }
-            if (lane == 0) {
-#pragma unroll
-                for (int k = 0; k < 3; ++k) lds.wave_first[wave][k] = d[kMinusX2[k]].w[0];
-            }
-            __syncthreads();
         }
+        if (lane == 63) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) lds.wave_last[wave][k] = d[kPlusX2[k]].w[NW - 1];
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) lds.wave_first[wave][k] = d[kMinusX2[k]].w[0];
+        }
+        __syncthreads();
         const uint32_t xl = (x0 == 0 ? nx : x0) - 1;
         const uint32_t xr = row_end ? 0 : x0 + V;
+        // the neighbour of a wave seam inside a row is a lane of this tile
+        const bool left_lds = x0 == 0 ? a.lds_edges != 0 : wave > 0;
+        const bool right_lds = row_end ? a.lds_edges != 0 : wave < kBlock / 64 - 1;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const int i = kPlusX2[k];
             uint32_t prev = wave_shr1(d[i].w[NW - 1]);
-            if (left_edge) prev = a.lds_edges ? (x0 == 0 ? lds.row_last[rit][k] : lds.wave_last[wave - 1][k])
-                                              : ld_elem<kF32>(src, rb[i] + xl);
+            if (left_edge) prev = left_lds ? (x0 == 0 ? lds.row_last[rit][k] : lds.wave_last[wave - 1][k])
+                                           : ld_elem<kF32>(src, rb[i] + xl);
             d[i] = shift_in_from_left<kF32, NW>(d[i], prev);
         }
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const int i = kMinusX2[k];
             uint32_t next = wave_shl1(d[i].w[0]);
-            if (right_edge) next = a.lds_edges ? (row_end ? lds.row_first[rit][k] : lds.wave_first[wave + 1][k])
-                                               : ld_elem<kF32>(src, rb[i] + xr);
+            if (right_edge) next = right_lds ? (row_end ? lds.row_first[rit][k] : lds.wave_first[wave + 1][k])
+                                             : ld_elem<kF32>(src, rb[i] + xr);
             d[i] = shift_in_from_right<kF32, NW>(d[i], next);
         }
 
