@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "lb.h"
+#include "lb_host.h"
 #include "lb_internal.h"
 
 using namespace lbm;
@@ -329,9 +330,9 @@ int enqueue_steps(lb_batch *b, int n)
 int time_steps(lb_batch *b, int warm, int n, double *ms)
 {
     if (int rc = enqueue_steps(b, warm)) return rc;
-    hipEvent_t e0, e1;
-    HIP_OR_FAIL(hipEventCreate(&e0));
-    HIP_OR_FAIL(hipEventCreate(&e1));
+    Events evs(2);
+    HIP_OR_FAIL(evs.create());
+    hipEvent_t e0 = evs[0], e1 = evs[1];
     int rc = LB_OK;
     if (hipEventRecord(e0, b->stream) != hipSuccess) rc = fail(LB_EHIP, "hipEventRecord");
     if (rc == LB_OK) rc = enqueue_steps(b, n);
@@ -339,8 +340,6 @@ int time_steps(lb_batch *b, int warm, int n, double *ms)
     float t = 0.0f;
     if (rc == LB_OK && hipEventSynchronize(e1) != hipSuccess) rc = fail(LB_EHIP, "hipEventSynchronize");
     if (rc == LB_OK && hipEventElapsedTime(&t, e0, e1) != hipSuccess) rc = fail(LB_EHIP, "hipEventElapsedTime");
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     if (rc == LB_OK) *ms = n > 0 ? (double)t / n : 0.0;
     return rc;
 }
@@ -711,8 +710,8 @@ int lb_batch_time_step_kernel(lb_batch *b, int n, double *ms)
 {
     if (int rc = check(b)) return rc;
     if (n < 1 || !ms) return fail(LB_EINVAL, "n >= 1 and a result pointer are required");
-    std::vector<hipEvent_t> ev(2 * n);
-    for (auto &e : ev) HIP_OR_FAIL(hipEventCreate(&e));
+    Events ev(2 * (size_t)n);
+    HIP_OR_FAIL(ev.create());
     int rc = LB_OK;
     for (int k = 0; k < n && rc == LB_OK; ++k) {
         BatchArgs a{};
@@ -748,7 +747,6 @@ int lb_batch_time_step_kernel(lb_batch *b, int n, double *ms)
         if (hipEventElapsedTime(&t, ev[2 * k], ev[2 * k + 1]) != hipSuccess) rc = fail(LB_EHIP, "hipEventElapsedTime");
         total += t;
     }
-    for (auto &e : ev) (void)hipEventDestroy(e);
     if (rc == LB_OK) *ms = total / n;
     return rc;
 }

@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "lb.h"
+#include "lb_host.h"
 #include "lb_internal.h"
 
 using namespace lbm;
@@ -763,9 +764,9 @@ int lb_time_steps(lb_lattice *h, int n, double *ms)
 {
     if (int rc = check(h)) return rc;
     if (n < 1 || !ms) return fail(LB_EINVAL, "n must be >= 1 and ms non-NULL");
-    hipEvent_t e0, e1;
-    HIP_OR_FAIL(hipEventCreate(&e0));
-    HIP_OR_FAIL(hipEventCreate(&e1));
+    Events evs(2);
+    HIP_OR_FAIL(evs.create());
+    hipEvent_t e0 = evs[0], e1 = evs[1];
     int rc = LB_OK;
     if (hipEventRecord(e0, h->stream) != hipSuccess) rc = fail(LB_EHIP, "hipEventRecord");
     if (rc == LB_OK) rc = enqueue_steps(h, n, nullptr, nullptr);
@@ -773,8 +774,6 @@ int lb_time_steps(lb_lattice *h, int n, double *ms)
     if (rc == LB_OK && hipEventSynchronize(e1) != hipSuccess) rc = fail(LB_EHIP, "hipEventSynchronize");
     float t = 0.0f;
     if (rc == LB_OK && hipEventElapsedTime(&t, e0, e1) != hipSuccess) rc = fail(LB_EHIP, "hipEventElapsedTime");
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     if (rc == LB_OK) *ms = t;
     return rc;
 }
@@ -818,9 +817,9 @@ int lb_copy_probe(lb_lattice *h, int reps, double *ms)
     if (int rc = check(h)) return rc;
     if (reps < 1 || !ms) return fail(LB_EINVAL, "reps must be >= 1 and ms non-NULL");
     const uint64_t bytes = ((uint64_t)h->arr_elems * h->esize) & ~(uint64_t)15;
-    hipEvent_t e0, e1;
-    HIP_OR_FAIL(hipEventCreate(&e0));
-    HIP_OR_FAIL(hipEventCreate(&e1));
+    Events evs(2);
+    HIP_OR_FAIL(evs.create());
+    hipEvent_t e0 = evs[0], e1 = evs[1];
     int rc = LB_OK;
     if (launch_copy(h->buf[h->cur], h->buf[h->cur ^ 1], bytes, h->stream) != hipSuccess)  // warm-up
         rc = fail(LB_EHIP, "copy kernel launch");
@@ -832,8 +831,6 @@ int lb_copy_probe(lb_lattice *h, int reps, double *ms)
     if (rc == LB_OK && hipEventSynchronize(e1) != hipSuccess) rc = fail(LB_EHIP, "hipEventSynchronize");
     float t = 0.0f;
     if (rc == LB_OK && hipEventElapsedTime(&t, e0, e1) != hipSuccess) rc = fail(LB_EHIP, "hipEventElapsedTime");
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     if (rc == LB_OK) *ms = t / reps;
     return rc;
 }

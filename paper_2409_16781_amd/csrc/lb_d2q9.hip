@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "lb.h"
+#include "lb_host.h"
 #include "lb_internal.h"
 
 using namespace lbm;
@@ -196,9 +197,9 @@ lb2d_lattice *lb2d_create(int nx, int ny, double tau, const uint8_t *flags, doub
     if ((e = hipMalloc(&h->ring, (size_t)kRingCap * 4 * sizeof(double))) != hipSuccess) return bail(LB_ENOMEM, "hipMalloc", e);
     if ((e = hipMalloc(&h->ticket, sizeof(unsigned int))) != hipSuccess) return bail(LB_ENOMEM, "hipMalloc", e);
     if ((e = hipMalloc(&h->counter, sizeof(unsigned long long))) != hipSuccess) return bail(LB_ENOMEM, "hipMalloc", e);
-    (void)hipMemsetAsync(h->ticket, 0, sizeof(unsigned int), h->stream);
-    (void)hipMemsetAsync(h->counter, 0, sizeof(unsigned long long), h->stream);
-    (void)hipMemsetAsync(h->ring, 0, (size_t)kRingCap * 4 * sizeof(double), h->stream);
+    if ((e = hipMemsetAsync(h->ticket, 0, sizeof(unsigned int), h->stream)) != hipSuccess) return bail(LB_EHIP, "hipMemsetAsync", e);
+    if ((e = hipMemsetAsync(h->counter, 0, sizeof(unsigned long long), h->stream)) != hipSuccess) return bail(LB_EHIP, "hipMemsetAsync", e);
+    if ((e = hipMemsetAsync(h->ring, 0, (size_t)kRingCap * 4 * sizeof(double), h->stream)) != hipSuccess) return bail(LB_EHIP, "hipMemsetAsync", e);
     if (h->solids) {
         if ((e = hipMalloc(&h->flags, n)) != hipSuccess) return bail(LB_ENOMEM, "hipMalloc(flags)", e);
         if ((e = hipMalloc(&h->nbmask, n * sizeof(uint32_t) + 64)) != hipSuccess) return bail(LB_ENOMEM, "hipMalloc(masks)", e);
@@ -318,9 +319,9 @@ int lb2d_time_steps(lb2d_lattice *h, int n, double *ms)
 {
     if (int rc = check2(h)) return rc;
     if (n < 1 || !ms) return fail(LB_EINVAL, "n >= 1 and a result pointer are required");
-    hipEvent_t e0, e1;
-    HIP_OR_FAIL(hipEventCreate(&e0));
-    HIP_OR_FAIL(hipEventCreate(&e1));
+    Events evs(2);
+    HIP_OR_FAIL(evs.create());
+    hipEvent_t e0 = evs[0], e1 = evs[1];
     int rc = LB_OK;
     if (hipEventRecord(e0, h->stream) != hipSuccess) rc = fail(LB_EHIP, "hipEventRecord");
     if (rc == LB_OK) rc = enqueue2(h, n);
@@ -328,8 +329,6 @@ int lb2d_time_steps(lb2d_lattice *h, int n, double *ms)
     float t = 0.0f;
     if (rc == LB_OK && hipEventSynchronize(e1) != hipSuccess) rc = fail(LB_EHIP, "hipEventSynchronize");
     if (rc == LB_OK && hipEventElapsedTime(&t, e0, e1) != hipSuccess) rc = fail(LB_EHIP, "hipEventElapsedTime");
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     if (rc == LB_OK) *ms = t;
     return rc;
 }
