@@ -221,7 +221,8 @@ def run_adjoint(torch, lbm, reps):
                 sites=n ** 3, fluid_sites=fl, steps=cfg["steps"], every=cfg["every"],
                 ms_per_gradient=round(dt * 1e3, 3),
                 site_steps_per_s=round(3 * cfg["steps"] * n ** 3 / dt / 1e6, 1),
-                note="forward + recompute + adjoint = 3 x steps site updates; includes allocation of the copies",
+                note="forward + recompute + adjoint = 3 x steps site updates; the sweep's buffers are kept by the lattice "
+                     "from the warm-up call on",
                 finite=bool(torch.isfinite(g).all()))
 
 

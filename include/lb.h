@@ -242,8 +242,8 @@ int lb_set_force_field(lb_lattice *lat, const float *fx);
  * with sum over the steps of dJ/dF_x(s) through the collisions; a term of J
  * that depends on the force directly is the caller's to add.  FP32 storage.
  * Device memory for ceil(nsteps / every) + min(every, nsteps) + 2 states is
- * allocated during the call and freed before it returns; the call
- * synchronises the stream.
+ * allocated by the first call that needs it and kept by the lattice for
+ * later calls (lb_destroy frees it); the call synchronises the stream.
  */
 int lb_grad_force_x(lb_lattice *lat, int nsteps, int every, const float *seed, float *grad);
 

@@ -87,6 +87,7 @@ struct lb_lattice {
     long long steps;
     hipGraphExec_t gexec;
     bool graph_ok;
+    std::vector<void *> adj_ws;  // state-sized buffers of the adjoint sweep, kept for later calls
 };
 
 namespace {
@@ -251,6 +252,8 @@ void release(lb_lattice *h)
                     h->gpartials, h->ticket,  h->ring,    h->counter, h->ffield};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
+    for (void *p : h->adj_ws) (void)hipFree(p);
+    h->adj_ws.clear();
 }
 
 int create_impl(lb_lattice **out, int nx, int ny, int nz, double tau, const uint8_t *flags, int storage,
@@ -560,32 +563,24 @@ int lb_grad_force_x(lb_lattice *h, int nsteps, int every, const float *seed, flo
     const size_t abytes = (size_t)h->arr_elems * sizeof(float);
     const int nck = (nsteps + every - 1) / every;
     const int seg = std::min(every, nsteps);
-    // device memory of the sweep: checkpoints, one segment of states, two adjoint arrays
-    std::vector<void *> mem;
-    auto grab = [&](size_t bytes) -> void * {
+    // device memory of the sweep: checkpoints, one segment of states, two
+    // adjoint arrays and the seed; the buffers are kept by the lattice and
+    // reused by later calls that need no more of them
+    const size_t need = (size_t)nck + (size_t)(seg - 1) + 3;
+    while (h->adj_ws.size() < need) {
         void *p = nullptr;
-        if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
-        mem.push_back(p);
-        return p;
-    };
-    auto cleanup = [&]() {
-        (void)hipStreamSynchronize(h->stream);
-        for (void *p : mem) (void)hipFree(p);
-    };
-    std::vector<char *> ck(nck), states(seg);
-    for (int k = 0; k < nck; ++k) ck[k] = static_cast<char *>(grab(abytes));
-    for (int k = 1; k < seg; ++k) states[k] = static_cast<char *>(grab(abytes));
-    char *nu[2] = {static_cast<char *>(grab(abytes)), static_cast<char *>(grab(abytes))};
-    char *lamN = static_cast<char *>(grab(abytes));
-    for (void *p : mem)
-        if (!p) {
-            cleanup();
-            return fail(LB_ENOMEM, "hipMalloc of the adjoint sweep (%d checkpoints of %zu bytes)", nck, abytes);
-        }
-    if ((int)mem.size() != nck + (seg - 1) + 3) {
-        cleanup();
-        return fail(LB_ENOMEM, "hipMalloc of the adjoint sweep (%d checkpoints of %zu bytes)", nck, abytes);
+        if (hipMalloc(&p, abytes) != hipSuccess)
+            return fail(LB_ENOMEM, "hipMalloc of the adjoint sweep (%zu states of %zu bytes)", need, abytes);
+        h->adj_ws.push_back(p);
     }
+    size_t next = 0;
+    auto grab = [&]() { return static_cast<char *>(h->adj_ws[next++]); };
+    auto cleanup = [&]() { (void)hipStreamSynchronize(h->stream); };
+    std::vector<char *> ck(nck), states(seg);
+    for (int k = 0; k < nck; ++k) ck[k] = grab();
+    for (int k = 1; k < seg; ++k) states[k] = grab();
+    char *nu[2] = {grab(), grab()};
+    char *lamN = grab();
     int rc = LB_OK;
     auto hip = [&](hipError_t e, const char *what) {
         if (rc == LB_OK && e != hipSuccess) rc = fail(LB_EHIP, "%s: %s", what, hipGetErrorString(e));
