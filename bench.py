@@ -46,6 +46,7 @@ def parse():
     p.add_argument("--no-adjoint", action="store_true", help="skip the 128^3 force-gradient leg")
     p.add_argument("--no-inplace", action="store_true", help="skip the one-array (in-place) FP32 leg")
     p.add_argument("--no-cavity", action="store_true", help="skip the 4096^2 D2Q9 lid-driven cavity leg")
+    p.add_argument("--no-small", action="store_true", help="skip the 32^3 box and 256x128x128 channel legs")
     return p.parse_args()
 
 
@@ -250,6 +251,46 @@ def run_cavity2d(torch, lbm, steps, reps):
                 finite_totals=bool(np.all(np.isfinite(sums))))
 
 
+def run_small(torch, lbm, reps):
+    """The two smaller D3Q19 workloads at their full step counts, FP32 and
+    FP16 storage: the 32^3 Taylor-Green box (200 steps; its 5 MB of state
+    stays in the caches, so it is no HBM roofline point) and the
+    256 x 128 x 128 force-driven channel (walls at y = 0 and 127, 5000 steps)."""
+    from paper_2409_16781_amd import inputs
+    out = {}
+    for key, cfg in (("tgv32", inputs.tgv_box(32)), ("channel256", inputs.channel())):
+        nz, ny, nx = cfg["shape"]
+        n = nx * ny * nz
+        entry = dict(workload=f"D3Q19 {cfg['name']}, tau={cfg['tau']}, force={cfg['force'][0]:g}, "
+                              f"{cfg['steps']} steps", sites=n, steps=cfg["steps"])
+        if cfg["flags"] is not None:
+            entry["fluid_sites"] = int((cfg["flags"] == 0).sum())
+        for codec in ("f32", "f16"):
+            lat = lbm.Lattice(nx, ny, nz, cfg["tau"], flags=cfg["flags"], codec=codec)
+            lat.set_force(*cfg["force"])
+            rho = torch.from_numpy(cfg["rho"]).cuda()
+            u = torch.from_numpy(cfg["u"]).cuda()
+            lat.init_eq(rho, u)
+            lat.step(64)  # warm-up: builds the step graphs
+            times = []
+            for _ in range(reps):
+                lat.init_eq(rho, u)
+                lat.sync()
+                times.append(lat.time_steps(cfg["steps"]))
+            ms = sorted(times)[reps // 2]
+            kernel_ms = lat.time_step_kernel(50)
+            sums = lat.sums(1)
+            lat.close()
+            entry[codec] = dict(mlups=round(n * cfg["steps"] / (ms * 1e-3) / 1e6, 1),
+                                ms_per_step=round(ms / cfg["steps"], 5),
+                                gbs_algorithmic=round(bytes_per_site(codec) * n * cfg["steps"] / (ms * 1e-3) / 1e9, 1),
+                                kernel_ms=round(kernel_ms, 5),
+                                kernel_gbs=round(bytes_per_site(codec) * n / (kernel_ms * 1e-3) / 1e9, 1),
+                                finite_totals=bool(np.all(np.isfinite(sums))))
+        out[key] = entry
+    return out
+
+
 def cpu_baseline(cfg, steps):
     """The FP64 oracle as it stands, on the host cores, for a few steps of the same lattice."""
     import oracle
@@ -347,6 +388,11 @@ def main():
         line["cavity4096_d2q9"] = run_cavity2d(torch, lbm, 2 * args.steps, args.reps)
         log(f"[bench] cavity4096: {line['cavity4096_d2q9']['mlups']:.0f} MLUPS, "
             f"{line['cavity4096_d2q9']['achieved_gbs']:.0f} GB/s")
+    if not args.no_small:
+        log("[bench] 32^3 Taylor-Green box and 256x128x128 channel, full step counts")
+        line.update(run_small(torch, lbm, args.reps))
+        for k in ("tgv32", "channel256"):
+            log(f"[bench] {k}: f32 {line[k]['f32']['mlups']:.0f} MLUPS, f16 {line[k]['f16']['mlups']:.0f} MLUPS")
     if not args.no_cpu:
         log(f"[bench] CPU baseline: oracle, {args.cpu_steps} steps")
         line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_steps)
