@@ -85,7 +85,7 @@ __device__ __forceinline__ uint32_t own_masks(const StepArgs &a, const TileGeom 
 #pragma unroll
     for (int e = 0; e < V; ++e) m[e] = 0;
     if constexpr (kSolids) {
-        if (a.rowdirty[g.row]) {
+        if (wave_dirty(a, g)) {
             load_masks<V>(a.nbmask + g.s0, m);
 #pragma unroll
             for (int e = 0; e < V; ++e) dead |= (m[e] >> 31) << e;

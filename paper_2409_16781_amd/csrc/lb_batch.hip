@@ -53,6 +53,7 @@ struct Domain {
     uint8_t *flags = nullptr;         // device copy (n bytes, zeros when all fluid)
     uint32_t *nbmask = nullptr;       // device, rows x pitch
     uint8_t *rowdirty = nullptr;      // device, rows
+    uint32_t *rowcum = nullptr;       // device, rows + 1 (dirty rows before each row)
     Layout lay{};
     uint64_t arr_elems = 0;           // elements of one population array
     void *buf[2] = {nullptr, nullptr};
@@ -123,6 +124,7 @@ void release_shape(lb_batch *b)
     for (Domain &d : b->dom) {
         free_dev(d.nbmask);
         free_dev(d.rowdirty);
+        free_dev(d.rowcum);
         d.buf[0] = d.buf[1] = nullptr;
     }
 }
@@ -155,6 +157,7 @@ StepArgs domain_args(const lb_batch *b, const Domain &d)
     a.coll = make_coll((float)d.omega, (float)d.force[0], (float)d.force[1], (float)d.force[2]);
     a.nbmask = d.nbmask;
     a.rowdirty = d.rowdirty;
+    a.rowcum = d.rowcum;
     return a;
 }
 
@@ -235,7 +238,10 @@ int configure(lb_batch *b, const Shape &s)
         if (e != hipSuccess) return fail(LB_ENOMEM, "hipMalloc(masks): %s", hipGetErrorString(e));
         e = hipMalloc(&d.rowdirty, rows);
         if (e != hipSuccess) return fail(LB_ENOMEM, "hipMalloc(rows): %s", hipGetErrorString(e));
-        HIP_OR_FAIL(launch_masks(d.flags, d.nx, d.ny, d.nz, (int)d.lay.pitch, d.nbmask, d.rowdirty, b->stream));
+        e = hipMalloc(&d.rowcum, (rows + 1) * sizeof(uint32_t));
+        if (e != hipSuccess) return fail(LB_ENOMEM, "hipMalloc(rows): %s", hipGetErrorString(e));
+        HIP_OR_FAIL(launch_masks(d.flags, d.nx, d.ny, d.nz, (int)d.lay.pitch, d.nbmask, d.rowdirty, d.rowcum,
+                                 b->stream));
         std::fill(tile_dom.begin() + d.tile_begin, tile_dom.begin() + d.tile_begin + d.ntiles, k);
     }
     e = hipMalloc(&b->d_doms, (size_t)b->count * sizeof(DomDesc));

@@ -9,13 +9,6 @@ namespace {
 // The domain table is read through the constant address space, so the
 // per-tile domain parameters (uniform per workgroup) come in with scalar
 // loads and live in scalar registers.
-// Address space 4 exists only in the device pass (the host pass parses the
-// kernel bodies but generates no code for them).
-#if defined(__HIP_DEVICE_COMPILE__)
-#define LB_CONSTANT_AS __attribute__((address_space(4)))
-#else
-#define LB_CONSTANT_AS
-#endif
 typedef LB_CONSTANT_AS const DomDesc ConstDomDesc;
 typedef LB_CONSTANT_AS const int ConstInt;
 

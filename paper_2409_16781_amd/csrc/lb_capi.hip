@@ -72,6 +72,7 @@ struct lb_lattice {
     float *ffield;    // per-site x-force added to force[0] (device, N floats), or nullptr
     uint32_t *nbmask;
     uint8_t *rowdirty;
+    uint32_t *rowcum;
     bool solids;
     double n_fluid;
     double *partials;
@@ -126,6 +127,7 @@ StepArgs step_args(const lb_lattice *h, int from, float *rho, float *u, int vari
     a.coll = make_coll((float)h->omega, (float)h->force[0], (float)h->force[1], (float)h->force[2]);
     a.nbmask = h->nbmask;
     a.rowdirty = h->rowdirty;
+    a.rowcum = h->rowcum;
     a.rho_out = rho;
     a.u_out = u;
     a.partials = h->partials;
@@ -248,8 +250,8 @@ void release(lb_lattice *h)
 {
     if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
-    void *ptrs[] = {h->alloc[0], h->alloc[1], h->flags,   h->nbmask, h->rowdirty, h->partials,
-                    h->gpartials, h->ticket,  h->ring,    h->counter, h->ffield};
+    void *ptrs[] = {h->alloc[0], h->alloc[1], h->flags,   h->nbmask, h->rowdirty, h->rowcum,
+                    h->partials, h->gpartials, h->ticket, h->ring,  h->counter, h->ffield};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (void *p : h->adj_ws) (void)hipFree(p);
@@ -412,8 +414,9 @@ int create_impl(lb_lattice **out, int nx, int ny, int nz, double tau, const uint
         if ((e = hipMalloc(&h->flags, n)) != hipSuccess) return bail(LB_ENOMEM, "hipMalloc(flags)", e);
         if ((e = hipMalloc(&h->nbmask, n * sizeof(uint32_t) + 64)) != hipSuccess) return bail(LB_ENOMEM, "hipMalloc(masks)", e);
         if ((e = hipMalloc(&h->rowdirty, (size_t)ny * nz)) != hipSuccess) return bail(LB_ENOMEM, "hipMalloc(rows)", e);
+        if ((e = hipMalloc(&h->rowcum, ((size_t)ny * nz + 1) * sizeof(uint32_t))) != hipSuccess) return bail(LB_ENOMEM, "hipMalloc(rows)", e);
         if ((e = hipMemcpyAsync(h->flags, flags, n, hipMemcpyHostToDevice, h->stream)) != hipSuccess) return bail(LB_EHIP, "hipMemcpyAsync(flags)", e);
-        if ((e = launch_masks(h->flags, nx, ny, nz, nx, h->nbmask, h->rowdirty, h->stream)) != hipSuccess) return bail(LB_EHIP, "mask kernels", e);
+        if ((e = launch_masks(h->flags, nx, ny, nz, nx, h->nbmask, h->rowdirty, h->rowcum, h->stream)) != hipSuccess) return bail(LB_EHIP, "mask kernels", e);
     }
     if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return bail(LB_EHIP, "hipStreamSynchronize", e);
     h->magic = kMagic;

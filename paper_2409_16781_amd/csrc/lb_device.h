@@ -610,6 +610,29 @@ __device__ __forceinline__ TileGeom tile_geom(const StepArgs &a, int tile)
     return g;
 }
 
+// Address space 4 (read-only, read through the scalar cache) exists only in
+// the device pass; the host pass parses the kernel bodies but generates no
+// code for them.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define LB_CONSTANT_AS __attribute__((address_space(4)))
+#else
+#define LB_CONSTANT_AS
+#endif
+typedef LB_CONSTANT_AS const uint32_t ConstU32;
+
+// Whether any site of the calling wave is solid or has a solid neighbour
+// (wave-uniform).  The lanes' rows are increasing, so the wave covers rows
+// r0..r1 of lanes 0 and 63; the answer comes from two scalar loads of the
+// dirty-row prefix count, with no vector-memory round trip.  All 64 lanes
+// must be active.
+__device__ __forceinline__ bool wave_dirty(const StepArgs &a, const TileGeom &g)
+{
+    const uint32_t r0 = __builtin_amdgcn_readfirstlane(g.row);
+    const uint32_t r1 = __builtin_amdgcn_readlane(g.row, 63);
+    const ConstU32 *rc = (const ConstU32 *)a.rowcum;
+    return rc[r1 + 1] != rc[r0];
+}
+
 // Pull gather of the 19 populations of a tile's sites from the stored array
 // src, with periodic wrap and halfway bounce-back: d[i] = src_i(x - c_i), or
 // src_opp(i)(x) where x - c_i is solid.  kSwap gathers the transpose used by
@@ -637,6 +660,16 @@ __device__ __forceinline__ uint32_t gather(const StepArgs &a, const char *src, c
     }
 #pragma unroll
     for (int i = 0; i < kQ; ++i) d[i] = ldv<NW, !kSolids>(src + (rb[i] + x0) * K::kBytes);
+    // Lattices: waves with a dead site or a bounce-back issue their
+    // neighbour masks right behind the pulls, the others read no mask at all.
+    // Batches (porous domains, nearly every wave dirty): a dirty byte per row,
+    // checked per lane once the pulls are in.
+    bool dirty = false;
+    uint32_t m[V];
+    if constexpr (kSolids && !kPadded) {
+        dirty = wave_dirty(a, g);
+        if (dirty) load_masks<V>(a.nbmask + g.s0, m);
+    }
 
     // +-1 shifts along x (all lanes take part in the DPP moves).  The element
     // a lane needs from beyond its wave or across the periodic wrap comes
@@ -715,21 +748,37 @@ __device__ __forceinline__ uint32_t gather(const StepArgs &a, const char *src, c
         for (int e = 1; e < V; ++e) dead |= (x0 + e >= nx ? 1u : 0u) << e;
     }
     if constexpr (kSolids) {
-        if (a.rowdirty[g.row]) {
-            uint32_t m[V];
-            load_masks<V>(a.nbmask + g.s0, m);
+        if constexpr (kPadded) {
+            dirty = a.rowdirty[g.row] != 0;
+            if (dirty) load_masks<V>(a.nbmask + g.s0, m);
+        }
+        if (dirty) {
 #pragma unroll
             for (int e = 0; e < V; ++e) dead |= (m[e] >> 31) << e;
+            // The site's own values replace the pulled ones.  A whole vector
+            // (and with FP32 storage a single element) is loaded straight
+            // into d[i], so these loads are all in flight together; a
+            // 16-bit vector with only some sites bouncing back is loaded
+            // whole and merged.
 #pragma unroll
             for (int i = 1; i < kQ; ++i) {
                 uint32_t sel = 0;  // bit e set: element e bounces back
 #pragma unroll
                 for (int e = 0; e < V; ++e) sel |= ((m[e] >> i) & 1u) << e;
-                if (sel) {
-                    const Lane<NW> o = ldv<NW>(src + (g.own + (kSwap ? i : OPP[i]) * a.lay.seg) * K::kBytes);
+                const char *op = src + (g.own + (kSwap ? i : OPP[i]) * a.lay.seg) * K::kBytes;
+                if (sel == (1u << V) - 1u) {
+                    d[i] = ldv<NW>(op);
+                } else if (sel) {
+                    if constexpr (K::kBytes == 4) {
 #pragma unroll
-                    for (int e = 0; e < V; ++e)
-                        if ((sel >> e) & 1u) vset<C, NW>(d[i], e, vget<C, NW>(o, e));
+                        for (int e = 0; e < V; ++e)
+                            if ((sel >> e) & 1u) d[i].w[e] = *reinterpret_cast<const uint32_t *>(op + 4 * e);
+                    } else {
+                        const Lane<NW> o = ldv<NW>(op);
+#pragma unroll
+                        for (int e = 0; e < V; ++e)
+                            if ((sel >> e) & 1u) vset<C, NW>(d[i], e, vget<C, NW>(o, e));
+                    }
                 }
             }
         }

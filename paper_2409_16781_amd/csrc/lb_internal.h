@@ -80,6 +80,7 @@ struct StepArgs {
     Coll coll;
     const uint32_t *nbmask;   // per site: bit i = site x - c_i is solid, bit 31 = site is solid
     const uint8_t *rowdirty;  // per row (y, z): 1 if any site of the row has a bit set in nbmask
+    const uint32_t *rowcum;   // rows + 1 entries: rowcum[r] = dirty rows before row r
     float *rho_out;           // optional macros output (N floats) or nullptr
     float *u_out;             // optional macros output (3N floats) or nullptr
     double *partials;         // out: 4 doubles per workgroup
@@ -186,9 +187,10 @@ hipError_t launch_totals(const TotalsArgs &a, hipStream_t s);
 hipError_t launch_init(int codec, const InitArgs &a, hipStream_t s);
 hipError_t launch_macros(int codec, const MacroArgs &a, hipStream_t s);
 // Neighbour masks of a (nx, ny, nz) lattice stored with row pitch >= nx
-// (mask of site (x, row) at row * pitch + x); rowdirty per row.
+// (mask of site (x, row) at row * pitch + x); rowdirty per row and its
+// exclusive prefix count rowcum (ny * nz + 1 entries).
 hipError_t launch_masks(const uint8_t *flags, int nx, int ny, int nz, int pitch, uint32_t *nbmask, uint8_t *rowdirty,
-                        hipStream_t s);
+                        uint32_t *rowcum, hipStream_t s);
 hipError_t launch_zero_solid_macros(const uint8_t *flags, int n, float *rho, float *u, hipStream_t s);
 hipError_t launch_copy(const void *src, void *dst, uint64_t bytes, hipStream_t s);
 int step_occupancy(int codec, int variant, bool solids, bool macros);  // workgroups per CU

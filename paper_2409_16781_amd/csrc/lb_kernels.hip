@@ -302,6 +302,41 @@ __global__ __launch_bounds__(kBlock) void build_rowdirty(const uint32_t *nbmask,
     }
 }
 
+// Exclusive prefix count of the dirty rows: rowcum[r] = dirty rows before row
+// r, for r = 0..nrows.  A wave covering rows r0..r1 holds a dead site or a
+// bounce-back exactly when rowcum[r1 + 1] != rowcum[r0].  One workgroup;
+// each pass covers kRowsPerThread rows per thread.
+__global__ __launch_bounds__(kBlock) void build_rowcum(const uint8_t *rowdirty, int64_t nrows, uint32_t *rowcum)
+{
+    constexpr int kRowsPerThread = 16;
+    __shared__ uint32_t scan[kBlock];
+    uint32_t carry = 0;
+    for (int64_t base = 0; base < nrows; base += (int64_t)kBlock * kRowsPerThread) {
+        const int64_t first = base + (int64_t)threadIdx.x * kRowsPerThread;
+        uint32_t count = 0;
+        for (int k = 0; k < kRowsPerThread; ++k)
+            if (first + k < nrows && rowdirty[first + k]) ++count;
+        scan[threadIdx.x] = count;
+        __syncthreads();
+        for (int off = 1; off < kBlock; off <<= 1) {
+            const uint32_t t = (int)threadIdx.x >= off ? scan[threadIdx.x - off] : 0u;
+            __syncthreads();
+            scan[threadIdx.x] += t;
+            __syncthreads();
+        }
+        uint32_t run = carry + scan[threadIdx.x] - count;  // dirty rows before `first`
+        for (int k = 0; k < kRowsPerThread; ++k) {
+            if (first + k < nrows) {
+                rowcum[first + k] = run;
+                if (rowdirty[first + k]) ++run;
+            }
+        }
+        carry += scan[kBlock - 1];
+        __syncthreads();  // scan[] is rewritten by the next pass
+    }
+    if (threadIdx.x == 0) rowcum[nrows] = carry;
+}
+
 // ------------------------------------------------------------- raw state --
 // Between raw population planes (19 x N elements, plane i holds population i
 // of every site in site order) and the storage layout.
@@ -487,10 +522,11 @@ hipError_t launch_macros(int codec, const MacroArgs &a, hipStream_t s)
 }
 
 hipError_t launch_masks(const uint8_t *flags, int nx, int ny, int nz, int pitch, uint32_t *nbmask, uint8_t *rowdirty,
-                        hipStream_t s)
+                        uint32_t *rowcum, hipStream_t s)
 {
     build_masks<<<grid_for((uint64_t)pitch * ny * nz), kBlock, 0, s>>>(flags, nx, ny, nz, pitch, nbmask);
     build_rowdirty<<<grid_for((uint64_t)ny * nz), kBlock, 0, s>>>(nbmask, pitch, ny * nz, rowdirty);
+    build_rowcum<<<1, kBlock, 0, s>>>(rowdirty, (int64_t)ny * nz, rowcum);
     return hipGetLastError();
 }
 
