@@ -77,6 +77,15 @@ __device__ __forceinline__ void add_totals(const Lane<NW> (&d)[kQ], double (&acc
     acc[3] += (double)pz;
 }
 
+// Wave budget of the in-place kernels: that of the two-array step for 4- and
+// 8-byte vectors, none for 16-byte vectors (their collision keeps pairs of
+// sites, which fits only at one wave per SIMD without spills).
+template <int C, int NW>
+constexpr int aa_waves()
+{
+    return NW <= 2 ? vec_waves<C, NW>() : 1;
+}
+
 // The lane's solid sites (bit e: site e is solid) and their neighbour masks.
 template <int V, bool kSolids>
 __device__ __forceinline__ uint32_t own_masks(const StepArgs &a, const TileGeom &g, uint32_t (&m)[V])
@@ -96,7 +105,7 @@ __device__ __forceinline__ uint32_t own_masks(const StepArgs &a, const TileGeom 
 
 // Odd -> even: read, collide, write swapped, all at the site itself.
 template <int C, int NW, bool kSolids>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(vec_waves<C, NW>()))) void aa_local(StepArgs a)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(aa_waves<C, NW>()))) void aa_local(StepArgs a)
 {
     using K = Codec<C>;
     constexpr int V = NW * 4 / K::kBytes;
@@ -148,7 +157,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(vec_wave
 template <int C, int NW>
 constexpr int push_waves()
 {
-    return (C == kF16 && NW <= 2) ? 2 : vec_waves<C, NW>();
+    return (C == kF16 && NW <= 2) ? 2 : aa_waves<C, NW>();
 }
 
 template <int C, int NW, bool kSolids>

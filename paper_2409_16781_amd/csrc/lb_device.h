@@ -550,15 +550,15 @@ __device__ __forceinline__ void load_masks(const uint32_t *p, uint32_t (&m)[V])
 
 // Register budget of the vector-row kernels, as waves per SIMD the compiler
 // must fit (the unrolled site loop otherwise favours latency over occupancy):
-// three for the 16-bit codecs with 4- or 8-byte vectors (fits without
-// spills), no constraint otherwise.
+// three for the 16-bit codecs with 4- or 8-byte vectors and two with 16-byte
+// vectors (both fit without spills), no constraint otherwise.
 template <int C, int NW>
 constexpr int vec_waves()
 {
 #ifdef LB_VEC_WAVES
     return LB_VEC_WAVES;
 #else
-    return (Codec<C>::kBytes == 2 && NW <= 2) ? 3 : 1;
+    return Codec<C>::kBytes == 2 ? (NW <= 2 ? 3 : 2) : 1;
 #endif
 }
 
@@ -843,6 +843,32 @@ __device__ __forceinline__ void tile_update(const StepArgs &a, const char *src, 
             }
 #pragma unroll
             for (int i = 0; i < kQ; ++i) d[i].w[e] = K::enc(gg[i]);
+        }
+    } else if constexpr (NW >= 4) {
+        // 16-byte vectors of 16-bit values (8 sites per lane): one site at a
+        // time, its results written back into its half of each dword, so
+        // the registers hold the loaded vectors plus one site.
+#pragma unroll
+        for (int j = 0; j < NW; ++j) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                float gg[kQ];
+#pragma unroll
+                for (int i = 0; i < kQ; ++i) gg[i] = K::dec(h ? d[i].w[j] >> 16 : d[i].w[j] & 0xffffu);
+                collide(gg, cp, mr[2 * j + h], mu[2 * j + h], mv[2 * j + h], mw[2 * j + h]);
+#pragma unroll
+                for (int i = 0; i < kQ; ++i) {
+                    const uint32_t b = K::enc(gg[i]);
+                    d[i].w[j] = h ? ((d[i].w[j] & 0xffffu) | (b << 16)) : ((d[i].w[j] & 0xffff0000u) | b);
+                }
+                // the packed words as they now stand: the next site decodes
+                // from these registers, so no two sites' values are live at once
+#pragma unroll
+                for (int i = 0; i < kQ; ++i) {
+#pragma unroll
+                    for (int k = 0; k < NW; ++k) asm volatile("" : "+v"(d[i].w[k]));
+                }
+            }
         }
     } else {
 #pragma unroll
