@@ -47,6 +47,8 @@ def parse():
     p.add_argument("--no-inplace", action="store_true", help="skip the one-array (in-place) FP32 leg")
     p.add_argument("--no-cavity", action="store_true", help="skip the 4096^2 D2Q9 lid-driven cavity leg")
     p.add_argument("--no-small", action="store_true", help="skip the 32^3 box and 256x128x128 channel legs")
+    p.add_argument("--small-steps", type=int, default=0,
+                   help="timed steps of the 32^3 box and channel legs (default 0: their own 200 and 5000)")
     return p.parse_args()
 
 
@@ -251,7 +253,7 @@ def run_cavity2d(torch, lbm, steps, reps):
                 finite_totals=bool(np.all(np.isfinite(sums))))
 
 
-def run_small(torch, lbm, reps):
+def run_small(torch, lbm, reps, steps=0):
     """The two smaller D3Q19 workloads at their full step counts, FP32 and
     FP16 storage: the 32^3 Taylor-Green box (200 steps; its 5 MB of state
     stays in the caches, so it is no HBM roofline point) and the
@@ -259,6 +261,8 @@ def run_small(torch, lbm, reps):
     from paper_2409_16781_amd import inputs
     out = {}
     for key, cfg in (("tgv32", inputs.tgv_box(32)), ("channel256", inputs.channel())):
+        if steps > 0:
+            cfg["steps"] = steps
         nz, ny, nx = cfg["shape"]
         n = nx * ny * nz
         entry = dict(workload=f"D3Q19 {cfg['name']}, tau={cfg['tau']}, force={cfg['force'][0]:g}, "
@@ -390,7 +394,7 @@ def main():
             f"{line['cavity4096_d2q9']['achieved_gbs']:.0f} GB/s")
     if not args.no_small:
         log("[bench] 32^3 Taylor-Green box and 256x128x128 channel, full step counts")
-        line.update(run_small(torch, lbm, args.reps))
+        line.update(run_small(torch, lbm, args.reps, args.small_steps))
         for k in ("tgv32", "channel256"):
             log(f"[bench] {k}: f32 {line[k]['f32']['mlups']:.0f} MLUPS, f16 {line[k]['f16']['mlups']:.0f} MLUPS")
     if not args.no_cpu:
