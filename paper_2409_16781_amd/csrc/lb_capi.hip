@@ -156,10 +156,11 @@ MacroArgs macro_args(const lb_lattice *h, int cur, float *rho, float *u)
     return a;
 }
 
-TotalsArgs totals_args(const lb_lattice *h)
+// Totals of the step whose workgroup partials are in buffer buf (0 or 1).
+TotalsArgs totals_args(const lb_lattice *h, int buf = 0)
 {
     TotalsArgs t{};
-    t.partials = h->partials;
+    t.partials = h->partials + (size_t)buf * 4 * h->grid;
     t.nparts = h->grid;
     t.gpartials = h->gpartials;
     t.ticket = h->ticket;
@@ -187,6 +188,30 @@ int enqueue_one(lb_lattice *h, int from, float *rho, float *u, hipStream_t s)
     return LB_OK;
 }
 
+// Enqueue count >= 1 steps without macros from buf[from] on stream s.  On
+// the vector-row kernels the steps form a run: step k writes its workgroup
+// partials into buffer k & 1, the first workgroup of step k + 1 appends the
+// totals of step k, and one totals kernel closes the run.  The ring then
+// holds the same values as with a totals kernel after every step.
+int enqueue_run(lb_lattice *h, int from, int count, hipStream_t s)
+{
+    if (h->inplace || h->variant == 0) {
+        for (int k = 0; k < count; ++k) {
+            int rc = enqueue_one(h, from ^ (k & 1), nullptr, nullptr, s);
+            if (rc) return rc;
+        }
+        return LB_OK;
+    }
+    for (int k = 0; k < count; ++k) {
+        StepArgs a = step_args(h, from ^ (k & 1), nullptr, nullptr);
+        a.partials = h->partials + (size_t)(k & 1) * 4 * h->grid;
+        if (k > 0) a.prev = totals_args(h, (k - 1) & 1);
+        HIP_OR_FAIL(launch_step(h->codec, h->variant, h->solids, false, a, h->grid, s));
+    }
+    HIP_OR_FAIL(launch_totals(totals_args(h, (count - 1) & 1), s));
+    return LB_OK;
+}
+
 int build_graph(lb_lattice *h)
 {
     if (h->graph_ok) return LB_OK;
@@ -196,8 +221,7 @@ int build_graph(lb_lattice *h)
     }
     if (!h->cap_stream) HIP_OR_FAIL(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
     HIP_OR_FAIL(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
-    int rc = LB_OK;
-    for (int k = 0; k < kGraphSteps && rc == LB_OK; ++k) rc = enqueue_one(h, k & 1, nullptr, nullptr, h->cap_stream);
+    int rc = enqueue_run(h, 0, kGraphSteps, h->cap_stream);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
     if (rc != LB_OK) {
@@ -231,11 +255,11 @@ int enqueue_steps(lb_lattice *h, int n, float *rho, float *u)
             plain -= kGraphSteps;
         }
     }
-    for (int k = 0; k < plain; ++k) {
-        int rc = enqueue_one(h, h->cur, nullptr, nullptr, h->stream);
+    if (plain > 0) {
+        int rc = enqueue_run(h, h->cur, plain, h->stream);
         if (rc) return rc;
-        h->cur ^= 1;
-        h->steps += 1;
+        h->cur ^= plain & 1;
+        h->steps += plain;
     }
     if (rho) {
         int rc = enqueue_one(h, h->cur, rho, u, h->stream);
@@ -400,9 +424,10 @@ int create_impl(lb_lattice **out, int nx, int ny, int nz, double tau, const uint
         if (e != hipSuccess) return bail(LB_EHIP, "hipMemsetAsync", e);
     }
     if (h->inplace) h->buf[1] = h->buf[0];  // steps read and write the one array
-    // per-step totals: one slot per step workgroup and one per reduce workgroup
+    // per-step totals: one slot per step workgroup (two buffers, for runs of
+    // steps) and one per reduce workgroup
     const size_t ngroups = ((size_t)h->grid + kRedChunk - 1) / kRedChunk;
-    if ((e = hipMalloc(&h->partials, (size_t)h->grid * 4 * sizeof(double))) != hipSuccess) return bail(LB_ENOMEM, "hipMalloc", e);
+    if ((e = hipMalloc(&h->partials, (size_t)h->grid * 8 * sizeof(double))) != hipSuccess) return bail(LB_ENOMEM, "hipMalloc", e);
     if ((e = hipMalloc(&h->gpartials, ngroups * 4 * sizeof(double))) != hipSuccess) return bail(LB_ENOMEM, "hipMalloc", e);
     if ((e = hipMalloc(&h->ticket, sizeof(unsigned int))) != hipSuccess) return bail(LB_ENOMEM, "hipMalloc", e);
     if ((e = hipMalloc(&h->ring, (size_t)kRingCap * 4 * sizeof(double))) != hipSuccess) return bail(LB_ENOMEM, "hipMalloc", e);
@@ -539,7 +564,7 @@ int lb_set_force_field(lb_lattice *h, const float *fx)
         (void)hipFree(h->gpartials);
         h->partials = h->gpartials = nullptr;
         const size_t ngroups = ((size_t)h->grid + kRedChunk - 1) / kRedChunk;
-        if (hipMalloc(&h->partials, (size_t)h->grid * 4 * sizeof(double)) != hipSuccess ||
+        if (hipMalloc(&h->partials, (size_t)h->grid * 8 * sizeof(double)) != hipSuccess ||
             hipMalloc(&h->gpartials, ngroups * 4 * sizeof(double)) != hipSuccess)
             return fail(LB_ENOMEM, "hipMalloc(partials)");
     }

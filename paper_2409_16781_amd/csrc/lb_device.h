@@ -455,6 +455,37 @@ __device__ __forceinline__ void block_sum4(const double *v, int count, double (&
     for (int k = 0; k < 4; ++k) out[k] = tot[k][0];
 }
 
+// The totals of one step from its workgroup partials t.partials, summed by a
+// single workgroup in the order of reduce_totals (each chunk of kRedChunk
+// partials, then the chunk sums, both in the same fixed trees, so the result
+// is bitwise the same) and appended to the ring.  The partials were written
+// by an earlier launch, so no fence is needed before reading them.
+__device__ __forceinline__ void append_step_totals(const TotalsArgs &t)
+{
+    const int nchunks = (t.nparts + kRedChunk - 1) / kRedChunk;
+    for (int c = 0; c < nchunks; ++c) {
+        double gs[4];
+        block_sum4(t.partials + 4 * (size_t)c * kRedChunk, min(kRedChunk, t.nparts - c * kRedChunk), gs, false);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                __hip_atomic_store(&t.gpartials[4 * c + k], gs[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();  // every thread has read the tree root before the next chunk rewrites it
+    }
+    double tot[4];
+    block_sum4(t.gpartials, nchunks, tot, true);
+    if (threadIdx.x == 0) {
+        const unsigned long long step = __hip_atomic_load(t.step_counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        double *r = t.ring + 4 * (step % kRingCap);
+        r[0] = t.n_fluid + tot[0];
+        r[1] = tot[1];
+        r[2] = tot[2];
+        r[3] = tot[3];
+        __hip_atomic_store(t.step_counter, step + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
 // ------------------------------------------------ step: vector-row kernel --
 // A lane owns V consecutive sites of one x-row (nx % V == 0) and moves one
 // 4-, 8- or 16-byte vector per population in each direction.  Lanes of a wave

@@ -66,6 +66,16 @@ Coll make_coll(float omega, float fx, float fy, float fz);
 
 constexpr int kRedChunk = 256;   // step-workgroup partials summed by one reduce workgroup (one per thread)
 
+struct TotalsArgs {
+    const double *partials;   // 4 doubles per step workgroup
+    int nparts;               // step workgroups
+    double *gpartials;        // 4 doubles per reduce workgroup
+    unsigned int *ticket;     // arrival counter, 0 between launches
+    double *ring;             // kRingCap x 4 doubles
+    unsigned long long *step_counter;
+    double n_fluid;           // number of fluid sites (exact in a double)
+};
+
 // Everything one step launch needs.  Pointers are device pointers.
 struct StepArgs {
     const void *src;          // stored state (post-collision of the previous step)
@@ -85,6 +95,8 @@ struct StepArgs {
     float *u_out;             // optional macros output (3N floats) or nullptr
     double *partials;         // out: 4 doubles per workgroup
     const float *fx_field;    // optional per-site x-force added to coll.fx (N floats, site order) or nullptr
+    TotalsArgs prev;          // prev.partials != nullptr: workgroup 0 also appends the totals of the
+                              // step whose partials these are (written by the previous launch) to the ring
 };
 
 // One lattice of a batch.  The step arguments of domain d are s, with the
@@ -146,15 +158,6 @@ struct Step2Args {
 };
 
 // The reduction of one step's partials into the ring of per-step totals.
-struct TotalsArgs {
-    const double *partials;   // 4 doubles per step workgroup
-    int nparts;               // step workgroups
-    double *gpartials;        // 4 doubles per reduce workgroup
-    unsigned int *ticket;     // arrival counter, 0 between launches
-    double *ring;             // kRingCap x 4 doubles
-    unsigned long long *step_counter;
-    double n_fluid;           // number of fluid sites (exact in a double)
-};
 
 struct InitArgs {
     void *dst;

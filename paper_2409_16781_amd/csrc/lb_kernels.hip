@@ -63,7 +63,10 @@ __global__ __launch_bounds__(kBlock) void reduce_totals(TotalsArgs a)
 }
 
 // One step of one lattice: one workgroup per tile (or a capped grid looping
-// over tiles); each workgroup stores the FP64 totals of its tiles.
+// over tiles); each workgroup stores the FP64 totals of its tiles.  In a run
+// of steps, workgroup 0 also appends the previous step's totals to the ring
+// (a.prev), so a run needs one totals kernel at its end instead of one per
+// step.
 template <int C, int NW, bool kSolids, bool kMacros, bool kFField = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(vec_waves<C, NW>()))) void step_vec(StepArgs a)
 {
@@ -75,6 +78,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(vec_wave
     for (int b = blockIdx.x; b < ntiles; b += gridDim.x)
         tile_update<C, NW, kSolids, kMacros, false, kFField>(a, src, dst, tile_of(b, ntiles, a.tile_order), acc, lds);
     store_block_totals(acc, a.partials + 4 * (size_t)blockIdx.x);
+    if (a.prev.partials != nullptr && blockIdx.x == 0) append_step_totals(a.prev);
 }
 
 // ---------------------------------------------- step: one site per thread --
