@@ -249,7 +249,7 @@ def run_cavity2d(torch, lbm, steps, reps):
                 ms_per_step=round(ms / steps, 4), bytes_per_site=72,
                 achieved_gbs=round(72 * n * steps / (ms * 1e-3) / 1e9, 1),
                 frac_hbm=round(72 * n * steps / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                note="time per step includes the FP64 totals reduction kernel",
+                note="time per step includes the FP64 totals (one totals kernel per run of steps)",
                 finite_totals=bool(np.all(np.isfinite(sums))))
 
 

@@ -89,22 +89,35 @@ Step2Args step2_args(const lb2d_lattice *h, int from)
     return a;
 }
 
+// Totals of the step whose workgroup partials are in buffer buf (0 or 1).
+TotalsArgs totals2(const lb2d_lattice *h, int buf)
+{
+    TotalsArgs t{};
+    t.partials = h->partials + (size_t)buf * 4 * h->grid;
+    t.nparts = h->grid;
+    t.gpartials = h->gpartials;
+    t.ticket = h->ticket;
+    t.ring = h->ring;
+    t.step_counter = h->counter;
+    t.n_fluid = h->n_fluid;
+    return t;
+}
+
+// n steps as one run: step k writes its workgroup partials into buffer k & 1
+// and the first workgroup of step k + 1 appends the totals of step k; one
+// totals kernel closes the run (the ring holds the same values as with one
+// totals kernel per step).
 int enqueue2(lb2d_lattice *h, int n)
 {
     for (int k = 0; k < n; ++k) {
-        HIP_OR_FAIL(launch_step2d(h->variant, h->solids, step2_args(h, h->cur), h->grid, h->stream));
-        TotalsArgs t{};
-        t.partials = h->partials;
-        t.nparts = h->grid;
-        t.gpartials = h->gpartials;
-        t.ticket = h->ticket;
-        t.ring = h->ring;
-        t.step_counter = h->counter;
-        t.n_fluid = h->n_fluid;
-        HIP_OR_FAIL(launch_totals(t, h->stream));
+        Step2Args a = step2_args(h, h->cur);
+        a.partials = h->partials + (size_t)(k & 1) * 4 * h->grid;
+        if (k > 0) a.prev = totals2(h, (k - 1) & 1);
+        HIP_OR_FAIL(launch_step2d(h->variant, h->solids, a, h->grid, h->stream));
         h->cur ^= 1;
         h->steps += 1;
     }
+    if (n > 0) HIP_OR_FAIL(launch_totals(totals2(h, (n - 1) & 1), h->stream));
     return LB_OK;
 }
 
@@ -192,7 +205,7 @@ lb2d_lattice *lb2d_create(int nx, int ny, double tau, const uint8_t *flags, doub
         if ((e = hipMemsetAsync(h->buf[b], 0, bytes, h->stream)) != hipSuccess) return bail(LB_EHIP, "hipMemsetAsync", e);
     }
     const size_t ngroups = ((size_t)h->grid + kRedChunk - 1) / kRedChunk;
-    if ((e = hipMalloc(&h->partials, (size_t)h->grid * 4 * sizeof(double))) != hipSuccess) return bail(LB_ENOMEM, "hipMalloc", e);
+    if ((e = hipMalloc(&h->partials, (size_t)h->grid * 8 * sizeof(double))) != hipSuccess) return bail(LB_ENOMEM, "hipMalloc", e);
     if ((e = hipMalloc(&h->gpartials, ngroups * 4 * sizeof(double))) != hipSuccess) return bail(LB_ENOMEM, "hipMalloc", e);
     if ((e = hipMalloc(&h->ring, (size_t)kRingCap * 4 * sizeof(double))) != hipSuccess) return bail(LB_ENOMEM, "hipMalloc", e);
     if ((e = hipMalloc(&h->ticket, sizeof(unsigned int))) != hipSuccess) return bail(LB_ENOMEM, "hipMalloc", e);

@@ -203,6 +203,7 @@ __global__ __launch_bounds__(kBlock) void step2d(Step2Args a)
         }
     }
     store_block_totals(acc, a.partials + 4 * (size_t)blockIdx.x);
+    if (a.prev.partials != nullptr && blockIdx.x == 0) append_step_totals(a.prev);
 }
 
 // bit i (1..8): site x - c_i is solid; bit 8 + i: it is the lid; bit 31: the site is solid.

@@ -155,6 +155,7 @@ struct Step2Args {
     const uint32_t *nbmask;   // bit i: site x - c_i solid; bit 8 + i: that site is the lid; bit 31: own solid
     const uint8_t *chunkdirty;  // per 64 sites (site s in chunk s / 64): any mask bit set
     double *partials;         // 4 doubles per workgroup (mass, px, py, 0)
+    TotalsArgs prev;          // as in StepArgs: the previous step's totals appended by workgroup 0
 };
 
 // The reduction of one step's partials into the ring of per-step totals.
