@@ -248,7 +248,7 @@ int configure(lb_batch *b, const Shape &s)
     if (e != hipSuccess) return fail(LB_ENOMEM, "hipMalloc(domain table): %s", hipGetErrorString(e));
     e = hipMalloc(&b->d_tile_dom, (size_t)tiles * sizeof(int));
     if (e != hipSuccess) return fail(LB_ENOMEM, "hipMalloc(tile list): %s", hipGetErrorString(e));
-    e = hipMalloc(&b->partials, (size_t)tiles * 4 * sizeof(double));
+    e = hipMalloc(&b->partials, (size_t)tiles * 8 * sizeof(double));  // two buffers, for runs of steps
     if (e != hipSuccess) return fail(LB_ENOMEM, "hipMalloc(partials): %s", hipGetErrorString(e));
     HIP_OR_FAIL(hipStreamSynchronize(b->stream));
     HIP_OR_FAIL(hipMemcpy(b->d_tile_dom, tile_dom.data(), tile_dom.size() * sizeof(int), hipMemcpyHostToDevice));
@@ -261,25 +261,43 @@ int configure(lb_batch *b, const Shape &s)
     return LB_OK;
 }
 
-int enqueue_one(lb_batch *b, int parity, hipStream_t s)
+// Totals of the batch step whose tile partials are in buffer buf (0 or 1).
+BatchTotalsArgs batch_totals_args(const lb_batch *b, int buf)
 {
-    BatchArgs a{};
-    a.doms = b->d_doms;
-    a.tile_dom = b->d_tile_dom;
-    a.ntiles = b->ntiles;
-    a.parity = parity;
-    a.tile_order = b->shape.tile_order;
-    a.partials = b->partials;
-    HIP_OR_FAIL(launch_batch_step(b->codec, b->shape.variant, a, b->grid, s));
     BatchTotalsArgs t{};
     t.doms = b->d_doms;
     t.ndoms = b->count;
-    t.partials = b->partials;
+    t.partials = b->partials + (size_t)buf * 4 * b->ntiles;
     t.ticket = b->ticket;
     t.ring = b->ring;
     t.step_counter = b->counter;
-    HIP_OR_FAIL(launch_batch_totals(t, s));
+    return t;
+}
+
+// count >= 1 steps from buf[parity] as one run: step k writes its tile
+// partials into buffer k & 1, the first workgroup of step k + 1 appends the
+// per-domain totals of step k, and one totals kernel closes the run (the
+// rings hold the same values as with one totals kernel per step).
+int enqueue_run(lb_batch *b, int parity, int count, hipStream_t s)
+{
+    for (int k = 0; k < count; ++k) {
+        BatchArgs a{};
+        a.doms = b->d_doms;
+        a.tile_dom = b->d_tile_dom;
+        a.ntiles = b->ntiles;
+        a.parity = parity ^ (k & 1);
+        a.tile_order = b->shape.tile_order;
+        a.partials = b->partials + (size_t)(k & 1) * 4 * b->ntiles;
+        if (k > 0) a.prev = batch_totals_args(b, (k - 1) & 1);
+        HIP_OR_FAIL(launch_batch_step(b->codec, b->shape.variant, a, b->grid, s));
+    }
+    HIP_OR_FAIL(launch_batch_totals(batch_totals_args(b, (count - 1) & 1), s));
     return LB_OK;
+}
+
+int enqueue_one(lb_batch *b, int parity, hipStream_t s)
+{
+    return enqueue_run(b, parity, 1, s);
 }
 
 int build_graph(lb_batch *b)
@@ -291,8 +309,7 @@ int build_graph(lb_batch *b)
     }
     if (!b->cap_stream) HIP_OR_FAIL(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
     HIP_OR_FAIL(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
-    int rc = LB_OK;
-    for (int k = 0; k < kBatchGraphSteps && rc == LB_OK; ++k) rc = enqueue_one(b, k & 1, b->cap_stream);
+    int rc = enqueue_run(b, 0, kBatchGraphSteps, b->cap_stream);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
     if (rc != LB_OK) {
@@ -324,10 +341,10 @@ int enqueue_steps(lb_batch *b, int n)
             plain -= kBatchGraphSteps;
         }
     }
-    for (int k = 0; k < plain; ++k) {
-        if (int rc = enqueue_one(b, b->cur, b->stream)) return rc;
-        b->cur ^= 1;
-        b->steps += 1;
+    if (plain > 0) {
+        if (int rc = enqueue_run(b, b->cur, plain, b->stream)) return rc;
+        b->cur ^= plain & 1;
+        b->steps += plain;
     }
     return LB_OK;
 }

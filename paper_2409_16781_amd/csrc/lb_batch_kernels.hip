@@ -12,6 +12,28 @@ namespace {
 typedef LB_CONSTANT_AS const DomDesc ConstDomDesc;
 typedef LB_CONSTANT_AS const int ConstInt;
 
+// The per-domain totals of one batch step from its tile partials, summed by
+// one workgroup exactly as reduce_domains does and appended to the rings.
+// The partials come from an earlier launch: no fence is needed.
+__device__ __forceinline__ void append_batch_totals(const BatchTotalsArgs &t)
+{
+    const unsigned long long step = __hip_atomic_load(t.step_counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int d = 0; d < t.ndoms; ++d) {
+        const DomDesc &D = t.doms[d];
+        double tot[4];
+        block_sum4(t.partials + 4 * (size_t)D.tile_begin, D.ntiles, tot, false);
+        if (threadIdx.x == 0) {
+            double *r = t.ring + 4 * ((size_t)d * kRingCap + step % kRingCap);
+            r[0] = D.n_fluid + tot[0];
+            r[1] = tot[1];
+            r[2] = tot[2];
+            r[3] = tot[3];
+        }
+        __syncthreads();  // every thread has read the tree root before the next domain rewrites it
+    }
+    if (threadIdx.x == 0) __hip_atomic_store(t.step_counter, step + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <int C, int NW>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(vec_waves<C, NW>()))) void step_batch(BatchArgs a)
 {
@@ -28,6 +50,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(vec_wave
         store_block_totals(acc, a.partials + 4 * (size_t)t);
         __syncthreads();  // the totals' LDS is reused by the next tile
     }
+    if (a.prev.partials != nullptr && blockIdx.x == 0) append_batch_totals(a.prev);
 }
 
 // Per-domain totals of a batch step: workgroup d sums the partials of domain

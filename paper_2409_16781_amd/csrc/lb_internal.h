@@ -109,16 +109,6 @@ struct DomDesc {
     double n_fluid;           // fluid sites of the domain
 };
 
-// A step of a batch: every tile of every domain in one launch.
-struct BatchArgs {
-    const DomDesc *doms;      // device table, one entry per domain
-    const int *tile_dom;      // per tile: its domain
-    int ntiles;               // tiles of all domains
-    int parity;               // source arrays are buf[parity]
-    int tile_order;           // as in StepArgs
-    double *partials;         // out: 4 doubles per tile
-};
-
 // Per-domain totals of one batch step: domain d sums the partials of its
 // tiles (in order) into ring[d][step % kRingCap].
 struct BatchTotalsArgs {
@@ -128,6 +118,17 @@ struct BatchTotalsArgs {
     unsigned int *ticket;     // arrival counter, 0 between launches
     double *ring;             // ndoms x kRingCap x 4 doubles
     unsigned long long *step_counter;
+};
+
+// A step of a batch: every tile of every domain in one launch.
+struct BatchArgs {
+    const DomDesc *doms;      // device table, one entry per domain
+    const int *tile_dom;      // per tile: its domain
+    int ntiles;               // tiles of all domains
+    int parity;               // source arrays are buf[parity]
+    int tile_order;           // as in StepArgs
+    double *partials;         // out: 4 doubles per tile
+    BatchTotalsArgs prev;     // prev.partials != nullptr: workgroup 0 also appends the previous step's totals
 };
 
 // One adjoint step (FP32 storage): see adjoint_vec in lb_kernels.hip.
