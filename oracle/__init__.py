@@ -150,10 +150,15 @@ def step(S, tau, F=None, flags=None, Fx_field=None, moments=False):
     return (out, rho, u) if moments else out
 
 
-def run(S, tau, nsteps, F=None, flags=None, Fx_field=None) -> np.ndarray:
-    """n steps; returns the new state (the input array is not modified)."""
+def run(S, tau, nsteps, F=None, flags=None, Fx_field=None, copy=True) -> np.ndarray:
+    """n steps; returns the new state.  The input array is not modified unless
+    copy=False, which advances a C-contiguous float64 S in place (one state
+    less in memory for the largest lattices)."""
     _, nz, ny, nx = S.shape
-    S = np.array(S, dtype=np.float64, order="C", copy=True)
+    if copy:
+        S = np.array(S, dtype=np.float64, order="C", copy=True)
+    elif S.dtype != np.float64 or not S.flags.c_contiguous:
+        raise ValueError("run(copy=False) needs a C-contiguous float64 state")
     fx = None if Fx_field is None else np.ascontiguousarray(Fx_field, dtype=np.float64)
     rc = _load().oracle_run(nx, ny, nz, _fp(flags, (nz, ny, nx)), 1.0 / tau, _dp(_vec3(F)),
                             _dp(fx), _dp(S), int(nsteps))

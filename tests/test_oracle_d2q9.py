@@ -141,3 +141,54 @@ def test_oracle_matches_independent_numpy_step():
         b = _numpy_step(b, 0.7, flags, (0.08, 0.0))
     m = flags == 0
     assert np.abs(a[:, m] - b[:, m]).max() < 1e-14
+
+
+# ------------------------------------------------------- oracle2_sums pins --
+# The velocity order of reading 20 written out here, not taken from the oracle.
+D2Q9_C = [(0, 0), (1, 0), (-1, 0), (0, 1), (0, -1), (1, 1), (1, -1), (-1, 1), (-1, -1)]
+
+
+def test_sums_of_single_populations_follow_the_velocity_order():
+    """One nonzero population i at one fluid site: the totals are
+    (v, c_ix v, c_iy v) with c_i from the written-out order, and a solid site's
+    values are left out."""
+    flags = np.zeros((3, 4), np.uint8)
+    flags[2, 3] = 1
+    for i, (cx, cy) in enumerate(D2Q9_C):
+        S = np.zeros((9, 3, 4))
+        S[i, 1, 2] = 0.375
+        S[i, 2, 3] = 5.0  # solid site: excluded
+        assert np.array_equal(oracle.d2_sums(S, flags), [0.375, cx * 0.375, cy * 0.375])
+
+
+def test_sums_of_a_uniform_flow_are_mass_times_velocity():
+    """A periodic box at uniform (rho, u): the equilibrium carries exactly rho u
+    per site (second-order Maxwell-Boltzmann truncation), so the totals are
+    N (rho, rho u_x, rho u_y); u_x and u_y differ in size and sign, so a
+    swapped or mis-signed component fails."""
+    ny, nx, rho, u = 5, 7, 1.01, (0.03, -0.02)
+    S = oracle.d2_init((ny, nx), rho=np.full((ny, nx), rho),
+                       u=np.stack([np.full((ny, nx), u[0]), np.full((ny, nx), u[1])]))
+    n = nx * ny
+    assert np.allclose(oracle.d2_sums(S), [n * rho, n * rho * u[0], n * rho * u[1]], rtol=0, atol=1e-13)
+    # invariant under steps (uniform flow on a periodic box is a fixed point)
+    S = oracle.d2_run(S, 0.7, 25)
+    assert np.allclose(oracle.d2_sums(S), [n * rho, n * rho * u[0], n * rho * u[1]], rtol=0, atol=1e-12)
+
+
+def test_sums_of_the_couette_strip_equal_the_exact_profile_integral():
+    """Steady plane Couette flow between the wall at y = 0 and the lid at
+    y = ny - 1 (speed U): rho = 1 (uniform pressure, mass exact up to FP64 rounding), and
+    u_x(y) = U (y - 1/2) / H on the H = ny - 2 fluid rows, so the total
+    x-momentum is U/H * sum_{y=1..H} (y - 1/2) = U H / 2 per column, and the
+    y-momentum is zero."""
+    ny, nx, U = 18, 3, 0.05
+    flags = np.zeros((ny, nx), np.uint8)
+    flags[0] = 1
+    flags[-1] = 2
+    S = oracle.d2_run(oracle.d2_init((ny, nx), flags=flags), 0.8, 20000, flags=flags, lid=(U, 0.0))
+    H = ny - 2
+    mass, px, py = oracle.d2_sums(S, flags)
+    assert abs(mass - nx * H) < 1e-9  # FP64 rounding over 20000 steps: ~5e-11
+    assert abs(px - nx * U * H / 2) < 1e-10
+    assert abs(py) < 1e-12
