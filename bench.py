@@ -206,14 +206,13 @@ def run_adjoint(torch, lbm, reps):
     u = torch.from_numpy(cfg["u"]).cuda()
     lat.set_force_field(torch.zeros((n, n, n), dtype=torch.float32, device="cuda"))
     lat.init_eq(rho, u)
-    seed = lbm.outlet_flux_seed(lat, fluid)
-    lat.grad_force_x(20, 10, seed)  # warm-up
+    lat.grad_outlet_flux_x(20, 10)  # warm-up
     times = []
     for _ in range(reps):
         lat.init_eq(rho, u)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        g = lat.grad_force_x(cfg["steps"], cfg["every"], seed)
+        _, g = lat.grad_outlet_flux_x(cfg["steps"], cfg["every"])
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
     dt = sorted(times)[len(times) // 2]

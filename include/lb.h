@@ -138,8 +138,10 @@ int lb_step(lb_lattice *lat, int n);
 int lb_step_macros(lb_lattice *lat, int n, float *rho, float *u);
 
 /*
- * Density and velocity of the current state, into caller-owned device arrays
- * rho (N floats) and u (3N floats, component-major):
+ * Density and velocity of the current state (the macroscopic moments of
+ * Section 2: density as the sum of the populations, momentum as their
+ * velocity-weighted sum), into caller-owned device arrays rho (N floats) and
+ * u (3N floats, component-major):
  *   rho = sum_i f_i,   u = (sum_i c_i f_i - F/2) / rho.
  * After a step these equal the pre-collision moments of that step (collision
  * keeps mass and the source adds exactly F to the momentum).  Solid sites get
@@ -151,16 +153,21 @@ int lb_macros(lb_lattice *lat, float *rho, float *u);
  * Copy the conservation totals of the last k steps into out[4*k] (host),
  * oldest first: {mass, momentum_x, momentum_y, momentum_z} summed over fluid
  * sites of each step's stored state (sum of f_i = w_i + g_i and of c_i g_i, as
- * stored), accumulated in FP64 on the GPU in a fixed order (bitwise
- * reproducible).  k must be <= min(steps taken since lb_init_eq, 4096).
+ * stored): the moments of Section 2 summed over the lattice, which the
+ * collision of Eq. 1 conserves (mass exactly, momentum up to the force F per
+ * fluid site and step).  Every stored value is converted to FP64 and summed
+ * in FP64 on the GPU in a fixed order (bitwise reproducible).  k must be <= min(steps taken since lb_init_eq, 4096).
  * Synchronises the stream.  Returns LB_EUNSTABLE when any copied value is
  * NaN or infinite (the values are still copied).
  */
 int lb_sums(lb_lattice *lat, double *out, int k);
 
 /*
- * Raw state in storage format: 19 planes of N elements (plane i = population
- * i, site order as above), each element the codec's value of g_i = f_i - w_i
+ * Raw state in storage format: the post-collision array of the fused scheme
+ * (Section 3.1: the array a step writes and the next step reads), e.g. for a
+ * checkpoint and restart of a run.  19 planes of N elements (plane i =
+ * population i, site order as above; the structure-of-arrays form of
+ * Section 3.1), each element the codec's value of g_i = f_i - w_i
  * (float for LB_F32, IEEE binary16 for LB_F16S, bfloat16 for LB_BF16S).
  * bytes must equal 19 * N * (4 or 2).  where is LB_HOST or LB_DEVICE.
  * Host copies synchronise; device copies are enqueued.  lb_set_f leaves the
@@ -246,6 +253,27 @@ int lb_set_force_field(lb_lattice *lat, const float *fx);
  * later calls (lb_destroy frees it); the call synchronises the stream.
  */
 int lb_grad_force_x(lb_lattice *lat, int nsteps, int every, const float *seed, float *grad);
+
+/*
+ * The outlet mass flux of the current state: J = sum over the fluid sites of
+ * the plane x = nx - 1 of rho u_x, with rho and u the moments of Section 2
+ * (u including the half-force shift of Guo's source term, Eq. 1), i.e.
+ * J = sum_i c_ix f_i - F_x / 2 per site with F_x the site's x-force.  Summed
+ * in FP64 on the GPU in a fixed order and stored in *J (HOST pointer).
+ * Two-array storage.  Synchronises the stream.
+ */
+int lb_outlet_flux(lb_lattice *lat, double *J);
+
+/*
+ * Gradient of the outlet mass flux J (lb_outlet_flux) of the state after
+ * nsteps steps with respect to the per-site x-force: lb_grad_force_x with the
+ * seed dJ/dS_N = c_ix at the fluid sites of the plane x = nx - 1 (built on the
+ * GPU), plus the direct term dJ/dF_x = -1/2 at those sites.  grad:
+ * caller-owned DEVICE array of N floats (site order), overwritten with the
+ * complete dJ/dF_x.  J: HOST pointer receiving J of the final state, or NULL.
+ * Same requirements, memory and synchronisation as lb_grad_force_x.
+ */
+int lb_grad_outlet_flux_x(lb_lattice *lat, int nsteps, int every, float *grad, double *J);
 
 /* ---- batches of lattices ------------------------------------------------- */
 

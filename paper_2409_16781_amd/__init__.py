@@ -49,6 +49,8 @@ _SIGNATURES = {
     "lb_copy_probe": (ctypes.c_int, [_P, ctypes.c_int, _P]),
     "lb_set_force_field": (ctypes.c_int, [_P, _P]),
     "lb_grad_force_x": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _P]),
+    "lb_outlet_flux": (ctypes.c_int, [_P, _P]),
+    "lb_grad_outlet_flux_x": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _P]),
     "lb2d_create": (_P, [ctypes.c_int, ctypes.c_int, ctypes.c_double, _P, ctypes.c_double, ctypes.c_double, _P]),
     "lb2d_destroy": (None, [_P]),
     "lb2d_init_eq": (ctypes.c_int, [_P, _P, _P]),
@@ -256,6 +258,24 @@ class Lattice:
         _check(lib().lb_grad_force_x(self._h, int(nsteps), int(every), _ptr(seed), _ptr(grad)), "lb_grad_force_x")
         return grad
 
+    def outlet_flux(self) -> float:
+        """J = sum of rho u_x over the fluid sites of the plane x = nx - 1 of
+        the current state (lb_outlet_flux; synchronises)."""
+        J = ctypes.c_double(0.0)
+        _check(lib().lb_outlet_flux(self._h, ctypes.byref(J)), "lb_outlet_flux")
+        return J.value
+
+    def grad_outlet_flux_x(self, nsteps: int, every: int):
+        """Advance nsteps steps; return (J, dJ/dF_x) of the outlet flux of the
+        final state (float, float32 CUDA tensor (nz, ny, nx))."""
+        import torch
+
+        grad = torch.empty((self.nz, self.ny, self.nx), dtype=torch.float32, device="cuda")
+        J = ctypes.c_double(0.0)
+        _check(lib().lb_grad_outlet_flux_x(self._h, int(nsteps), int(every), _ptr(grad), ctypes.byref(J)),
+               "lb_grad_outlet_flux_x")
+        return J.value, grad
+
     @property
     def steps_done(self) -> int:
         return int(lib().lb_steps_done(self._h))
@@ -385,27 +405,10 @@ class Lattice2D:
         return ms.value
 
 
-WEIGHTS_D2Q9 = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
-
-C_X = np.array([0, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1, 0, 0, 0, 0])
-
-
-def outlet_flux(lat: "Lattice"):
-    """J = sum of rho u_x over the fluid sites of the plane x = nx - 1 (a
-    float64 CUDA scalar), from the lattice's current state."""
-    rho, u = lat.macros()
-    return (rho[:, :, -1].double() * u[0, :, :, -1].double()).sum()
-
-
-def outlet_flux_seed(lat: "Lattice", fluid):
-    """dJ/dS_N of the outlet flux: c_ix at the fluid sites of x = nx - 1.
-    fluid: bool CUDA tensor (nz, ny, nx)."""
-    import torch
-
-    seed = torch.zeros((19, lat.nz, lat.ny, lat.nx), dtype=torch.float32, device="cuda")
-    cx = torch.tensor(C_X, dtype=torch.float32, device="cuda")
-    seed[:, :, :, -1] = cx[:, None, None] * fluid[None, :, :, -1].float()
-    return seed
+def outlet_flux(lat: "Lattice") -> float:
+    """J = sum of rho u_x over the fluid sites of the plane x = nx - 1 of the
+    lattice's current state (computed by the library)."""
+    return lat.outlet_flux()
 
 
 def _outlet_flux_function():
@@ -419,34 +422,32 @@ def _outlet_flux_function():
         the lattice is left at step nsteps after either pass."""
 
         @staticmethod
-        def forward(ctx, fx, lat, nsteps, every, fluid):
+        def forward(ctx, fx, lat, nsteps, every):
             state0 = torch.empty((19, lat.nz, lat.ny, lat.nx), dtype=torch.float32, device="cuda")
             lat.get_f_device(state0)
             lat.set_force_field(fx.detach().contiguous())
             lat.step(nsteps)
-            J = outlet_flux(lat)
+            J = torch.tensor(lat.outlet_flux(), dtype=torch.float64, device="cuda")
             ctx.lat, ctx.nsteps, ctx.every = lat, nsteps, every
-            ctx.save_for_backward(fx.detach(), state0, fluid)
+            ctx.save_for_backward(fx.detach(), state0)
             return J
 
         @staticmethod
         def backward(ctx, gJ):
-            fx, state0, fluid = ctx.saved_tensors
+            fx, state0 = ctx.saved_tensors
             lat = ctx.lat
             lat.set_f_device(state0)
             lat.set_force_field(fx.contiguous())
-            g = lat.grad_force_x(ctx.nsteps, ctx.every, outlet_flux_seed(lat, fluid))
-            g = g.double()
-            g[:, :, -1] -= 0.5 * fluid[:, :, -1].double()  # J holds -F_x / 2 at each outlet site
-            return (gJ * g).to(fx.dtype), None, None, None, None
+            _, g = lat.grad_outlet_flux_x(ctx.nsteps, ctx.every)
+            return (gJ * g.double()).to(fx.dtype), None, None, None
 
     return OutletFlux
 
 
-def outlet_flux_autograd(fx, lat: "Lattice", nsteps: int, every: int, fluid):
+def outlet_flux_autograd(fx, lat: "Lattice", nsteps: int, every: int):
     """Differentiable outlet flux: torch.autograd sees J as a function of the
     per-site x-force fx (float32 CUDA tensor (nz, ny, nx))."""
-    return _outlet_flux_function().apply(fx, lat, int(nsteps), int(every), fluid)
+    return _outlet_flux_function().apply(fx, lat, int(nsteps), int(every))
 
 
 class Batch:

@@ -51,32 +51,6 @@ __device__ __forceinline__ void collide_lane(Lane<NW> (&d)[kQ], const Coll &cp)
     }
 }
 
-// FP64 totals of a lane's collided values (dead elements already zero).
-template <int C, int NW>
-__device__ __forceinline__ void add_totals(const Lane<NW> (&d)[kQ], double (&acc)[4])
-{
-    using K = Codec<C>;
-    float tot[kQ];
-#pragma unroll
-    for (int i = 0; i < kQ; ++i) {
-        float t = 0.0f;
-#pragma unroll
-        for (int j = 0; j < NW; ++j) {
-            if constexpr (K::kBytes == 4)
-                t += K::dec(d[i].w[j]);
-            else
-                t = K::sum2(d[i].w[j], t);
-        }
-        tot[i] = t;
-    }
-    float m, px, py, pz;
-    moments_of_totals(tot, m, px, py, pz);
-    acc[0] += (double)m;
-    acc[1] += (double)px;
-    acc[2] += (double)py;
-    acc[3] += (double)pz;
-}
-
 // Wave budget of the in-place kernels: that of the two-array step for 4- and
 // 8-byte vectors, none for 16-byte vectors (their collision keeps pairs of
 // sites, which fits only at one wave per SIMD without spills).
@@ -142,7 +116,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(aa_waves
                             if (!((dead >> e) & 1u)) st_elem<C>(F, g.own + OPP[i] * a.lay.seg + e, vget<C, NW>(d[i], e));
                 }
             }
-            add_totals<C, NW>(d, acc);
+            add_lane_totals<C, NW>(d, acc);
         }
     }
     store_block_totals(acc, a.partials + 4 * (size_t)blockIdx.x);
@@ -191,7 +165,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(push_wav
                 }
         }
         if (g.active) {
-            add_totals<C, NW>(d, acc);
+            add_lane_totals<C, NW>(d, acc);
             // bounce-back: where x + c_i is solid (bit opp(i)), f*_i(x) stays at x, in slot opp(i)
             if constexpr (kSolids) {
 #pragma unroll

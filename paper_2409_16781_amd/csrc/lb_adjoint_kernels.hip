@@ -132,7 +132,97 @@ __global__ __launch_bounds__(kBlock) void adjoint_vec(AdjArgs a)
     }
 }
 
+// ----------------------------------------------------- outlet mass flux --
+// J = sum over the fluid sites of the plane x = nx - 1 of rho u_x.  With the
+// moments of Section 2 and the Guo half-force shift, rho u_x of a stored
+// post-collision state S is sum_i c_ix S_i - F_x / 2 (collision adds exactly F
+// to the momentum); the shift by the weights drops out (sum_i w_i c_ix = 0).
+// dJ/dS_i = c_ix at those sites, and J depends on the force directly through
+// -F_x / 2.
+
+__device__ __forceinline__ bool outlet_fluid(const OutletArgs &a, uint32_t row, uint64_t &site)
+{
+    site = (uint64_t)row * a.nx + (uint64_t)(a.nx - 1);
+    return !(a.flags && a.flags[site]);
+}
+
+// One workgroup: each thread sums its rows in order, then a fixed LDS tree.
+template <int C>
+__global__ __launch_bounds__(kBlock) void outlet_flux_kernel(OutletArgs a)
+{
+    using K = Codec<C>;
+    __shared__ double red[kBlock];
+    const char *src = reinterpret_cast<const char *>(a.state);
+    const uint32_t rows = (uint32_t)a.ny * (uint32_t)a.nz;
+    double acc = 0.0;
+    for (uint32_t r = threadIdx.x; r < rows; r += kBlock) {
+        uint64_t site;
+        if (!outlet_fluid(a, r, site)) continue;
+        const uint64_t own = a.lay.row_base(r) + (uint64_t)(a.nx - 1);
+        double jx = 0.0;
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) {
+            if (CX[i] == 0) continue;
+            const double v = (double)K::dec(ld_elem<C>(src, own + i * a.lay.seg));
+            jx = CX[i] > 0 ? jx + v : jx - v;
+        }
+        const double F = (double)a.fx + (a.fx_field ? (double)a.fx_field[site] : 0.0);
+        acc += jx - 0.5 * F;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kBlock / 2; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) a.J[0] = red[0];
+}
+
+// dJ/dS_N: c_ix at population i of each outlet fluid site (the rest of the
+// array was zeroed by the caller).  One thread per (row, population).
+__global__ __launch_bounds__(kBlock) void outlet_seed_kernel(OutletArgs a)
+{
+    const uint64_t rows = (uint64_t)a.ny * (uint64_t)a.nz;
+    for (uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x; t < rows * kQ; t += (uint64_t)gridDim.x * kBlock) {
+        const uint32_t r = (uint32_t)(t / kQ);
+        const int i = (int)(t - (uint64_t)r * kQ);
+        uint64_t site;
+        if (CX[i] == 0 || !outlet_fluid(a, r, site)) continue;
+        a.seed[a.lay.row_base(r) + (uint64_t)i * a.lay.seg + (uint64_t)(a.nx - 1)] = (float)CX[i];
+    }
+}
+
+// The direct term dJ/dF_x = -1/2 at each outlet fluid site.
+__global__ __launch_bounds__(kBlock) void outlet_direct_kernel(OutletArgs a)
+{
+    const uint64_t rows = (uint64_t)a.ny * (uint64_t)a.nz;
+    for (uint64_t r = (uint64_t)blockIdx.x * kBlock + threadIdx.x; r < rows; r += (uint64_t)gridDim.x * kBlock) {
+        uint64_t site;
+        if (outlet_fluid(a, (uint32_t)r, site)) a.grad[site] -= 0.5f;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_outlet_flux(int codec, const OutletArgs &a, hipStream_t s)
+{
+    if (codec == kF32) outlet_flux_kernel<kF32><<<1, kBlock, 0, s>>>(a);
+    else if (codec == kF16) outlet_flux_kernel<kF16><<<1, kBlock, 0, s>>>(a);
+    else outlet_flux_kernel<kBF16><<<1, kBlock, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_outlet_seed(const OutletArgs &a, hipStream_t s)
+{
+    outlet_seed_kernel<<<grid_for((uint64_t)a.ny * a.nz * kQ), kBlock, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_outlet_direct(const OutletArgs &a, hipStream_t s)
+{
+    outlet_direct_kernel<<<grid_for((uint64_t)a.ny * a.nz), kBlock, 0, s>>>(a);
+    return hipGetLastError();
+}
 
 namespace {
 template <int NW, bool S>

@@ -89,6 +89,8 @@ struct lb_lattice {
     hipGraphExec_t gexec;
     bool graph_ok;
     std::vector<void *> adj_ws;  // state-sized buffers of the adjoint sweep, kept for later calls
+    double *jval;     // device double: the outlet flux objective
+    int dev;          // HIP device the lattice lives on
 };
 
 namespace {
@@ -156,14 +158,25 @@ MacroArgs macro_args(const lb_lattice *h, int cur, float *rho, float *u)
     return a;
 }
 
+// Device buffers of the per-step totals: the step workgroups' partials (two
+// buffers of grid slots, for runs of steps), the reduce workgroups' partials
+// and the reduce's arrival ticket.
+struct TotalsBufs {
+    double *partials;
+    double *gpartials;
+    unsigned int *ticket;
+};
+
+TotalsBufs own_bufs(const lb_lattice *h) { return TotalsBufs{h->partials, h->gpartials, h->ticket}; }
+
 // Totals of the step whose workgroup partials are in buffer buf (0 or 1).
-TotalsArgs totals_args(const lb_lattice *h, int buf = 0)
+TotalsArgs totals_args(const lb_lattice *h, int buf, const TotalsBufs &tb)
 {
     TotalsArgs t{};
-    t.partials = h->partials + (size_t)buf * 4 * h->grid;
+    t.partials = tb.partials + (size_t)buf * 4 * h->grid;
     t.nparts = h->grid;
-    t.gpartials = h->gpartials;
-    t.ticket = h->ticket;
+    t.gpartials = tb.gpartials;
+    t.ticket = tb.ticket;
     t.ring = h->ring;
     t.step_counter = h->counter;
     t.n_fluid = h->n_fluid;
@@ -171,18 +184,19 @@ TotalsArgs totals_args(const lb_lattice *h, int buf = 0)
 }
 
 // Enqueue one step from buf[from] on stream s.
-int enqueue_one(lb_lattice *h, int from, float *rho, float *u, hipStream_t s)
+int enqueue_one(lb_lattice *h, int from, float *rho, float *u, hipStream_t s, const TotalsBufs &tb)
 {
     const bool macros = rho != nullptr;
     StepArgs a = step_args(h, from, rho, u);
+    a.partials = tb.partials;
     if (h->inplace) {
         HIP_OR_FAIL(launch_aa_step(h->codec, h->variant, h->solids, from == 0, a, h->grid, s));
-        HIP_OR_FAIL(launch_totals(totals_args(h), s));
+        HIP_OR_FAIL(launch_totals(totals_args(h, 0, tb), s));
         if (macros) HIP_OR_FAIL(launch_macros(h->codec, macro_args(h, from ^ 1, rho, u), s));
         return LB_OK;
     }
     HIP_OR_FAIL(launch_step(h->codec, h->variant, h->solids, macros, a, h->grid, s));
-    HIP_OR_FAIL(launch_totals(totals_args(h), s));
+    HIP_OR_FAIL(launch_totals(totals_args(h, 0, tb), s));
     if (macros && h->solids && h->variant == 0)
         HIP_OR_FAIL(launch_zero_solid_macros(h->flags, (int)h->n, rho, u, s));
     return LB_OK;
@@ -193,22 +207,22 @@ int enqueue_one(lb_lattice *h, int from, float *rho, float *u, hipStream_t s)
 // partials into buffer k & 1, the first workgroup of step k + 1 appends the
 // totals of step k, and one totals kernel closes the run.  The ring then
 // holds the same values as with a totals kernel after every step.
-int enqueue_run(lb_lattice *h, int from, int count, hipStream_t s)
+int enqueue_run(lb_lattice *h, int from, int count, hipStream_t s, const TotalsBufs &tb)
 {
     if (h->inplace || h->variant == 0) {
         for (int k = 0; k < count; ++k) {
-            int rc = enqueue_one(h, from ^ (k & 1), nullptr, nullptr, s);
+            int rc = enqueue_one(h, from ^ (k & 1), nullptr, nullptr, s, tb);
             if (rc) return rc;
         }
         return LB_OK;
     }
     for (int k = 0; k < count; ++k) {
         StepArgs a = step_args(h, from ^ (k & 1), nullptr, nullptr);
-        a.partials = h->partials + (size_t)(k & 1) * 4 * h->grid;
-        if (k > 0) a.prev = totals_args(h, (k - 1) & 1);
+        a.partials = tb.partials + (size_t)(k & 1) * 4 * h->grid;
+        if (k > 0) a.prev = totals_args(h, (k - 1) & 1, tb);
         HIP_OR_FAIL(launch_step(h->codec, h->variant, h->solids, false, a, h->grid, s));
     }
-    HIP_OR_FAIL(launch_totals(totals_args(h, (count - 1) & 1), s));
+    HIP_OR_FAIL(launch_totals(totals_args(h, (count - 1) & 1, tb), s));
     return LB_OK;
 }
 
@@ -221,7 +235,7 @@ int build_graph(lb_lattice *h)
     }
     if (!h->cap_stream) HIP_OR_FAIL(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
     HIP_OR_FAIL(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
-    int rc = enqueue_run(h, 0, kGraphSteps, h->cap_stream);
+    int rc = enqueue_run(h, 0, kGraphSteps, h->cap_stream, own_bufs(h));
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
     if (rc != LB_OK) {
@@ -241,7 +255,7 @@ int enqueue_steps(lb_lattice *h, int n, float *rho, float *u)
     int plain = rho ? n - 1 : n;
     if (plain >= 2 * kGraphSteps) {
         if (h->cur == 1) {
-            int rc = enqueue_one(h, 1, nullptr, nullptr, h->stream);
+            int rc = enqueue_one(h, 1, nullptr, nullptr, h->stream, own_bufs(h));
             if (rc) return rc;
             h->cur = 0;
             h->steps += 1;
@@ -256,13 +270,13 @@ int enqueue_steps(lb_lattice *h, int n, float *rho, float *u)
         }
     }
     if (plain > 0) {
-        int rc = enqueue_run(h, h->cur, plain, h->stream);
+        int rc = enqueue_run(h, h->cur, plain, h->stream, own_bufs(h));
         if (rc) return rc;
         h->cur ^= plain & 1;
         h->steps += plain;
     }
     if (rho) {
-        int rc = enqueue_one(h, h->cur, rho, u, h->stream);
+        int rc = enqueue_one(h, h->cur, rho, u, h->stream, own_bufs(h));
         if (rc) return rc;
         h->cur ^= 1;
         h->steps += 1;
@@ -275,7 +289,7 @@ void release(lb_lattice *h)
     if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     void *ptrs[] = {h->alloc[0], h->alloc[1], h->flags,   h->nbmask, h->rowdirty, h->rowcum,
-                    h->partials, h->gpartials, h->ticket, h->ring,  h->counter, h->ffield};
+                    h->partials, h->gpartials, h->ticket, h->ring,  h->counter, h->ffield, h->jval};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (void *p : h->adj_ws) (void)hipFree(p);
@@ -394,6 +408,7 @@ int create_impl(lb_lattice **out, int nx, int ny, int nz, double tau, const uint
         return fail(LB_EHIP, "cannot query the HIP device");
     }
     h->cus = prop.multiProcessorCount;
+    h->dev = dev;
     // One workgroup per tile of kBlock lanes.  LB_WG_PER_CU caps the grid at
     // that many workgroups per compute unit (each then loops over tiles).
     const uint64_t tiles = (n / h->vsites + kBlock - 1) / kBlock;
@@ -432,6 +447,7 @@ int create_impl(lb_lattice **out, int nx, int ny, int nz, double tau, const uint
     if ((e = hipMalloc(&h->ticket, sizeof(unsigned int))) != hipSuccess) return bail(LB_ENOMEM, "hipMalloc", e);
     if ((e = hipMalloc(&h->ring, (size_t)kRingCap * 4 * sizeof(double))) != hipSuccess) return bail(LB_ENOMEM, "hipMalloc", e);
     if ((e = hipMalloc(&h->counter, sizeof(unsigned long long))) != hipSuccess) return bail(LB_ENOMEM, "hipMalloc", e);
+    if ((e = hipMalloc(&h->jval, 256)) != hipSuccess) return bail(LB_ENOMEM, "hipMalloc", e);
     if ((e = hipMemsetAsync(h->ticket, 0, sizeof(unsigned int), h->stream)) != hipSuccess) return bail(LB_EHIP, "hipMemsetAsync", e);
     if ((e = hipMemsetAsync(h->counter, 0, sizeof(unsigned long long), h->stream)) != hipSuccess) return bail(LB_EHIP, "hipMemsetAsync", e);
     if ((e = hipMemsetAsync(h->ring, 0, (size_t)kRingCap * 4 * sizeof(double), h->stream)) != hipSuccess) return bail(LB_EHIP, "hipMemsetAsync", e);
@@ -572,13 +588,45 @@ int lb_set_force_field(lb_lattice *h, const float *fx)
     return LB_OK;
 }
 
-int lb_grad_force_x(lb_lattice *h, int nsteps, int every, const float *seed, float *grad)
+}  // extern "C"
+
+namespace {
+
+OutletArgs outlet_args(const lb_lattice *h, const void *state)
+{
+    OutletArgs a{};
+    a.state = state;
+    a.J = h->jval;
+    a.lay = h->lay;
+    a.nx = h->nx;
+    a.ny = h->ny;
+    a.nz = h->nz;
+    a.flags = h->flags;
+    a.fx = (float)h->force[0];
+    a.fx_field = h->ffield;
+    return a;
+}
+
+// The outlet flux of the state in buf[h->cur] into *J (host); synchronises.
+int outlet_flux_value(lb_lattice *h, double *J)
+{
+    HIP_OR_FAIL(launch_outlet_flux(h->codec, outlet_args(h, h->buf[h->cur]), h->stream));
+    HIP_OR_FAIL(hipMemcpyAsync(J, h->jval, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIP_OR_FAIL(hipStreamSynchronize(h->stream));
+    return LB_OK;
+}
+
+// Checkpointed adjoint sweep of nsteps steps.  The objective's seed dJ/dS_N
+// is the caller's raw planes (seed != nullptr) or the outlet flux's (seed ==
+// nullptr, which also adds the flux's direct term and stores J in *J when J
+// is not null).
+int grad_impl(lb_lattice *h, int nsteps, int every, const float *seed, float *grad, double *J)
 {
     if (int rc = check(h)) return rc;
     if (h->codec != kF32) return fail(LB_EINVAL, "the adjoint needs FP32 storage");
     if (h->inplace) return fail(LB_EINVAL, "the adjoint needs two-array storage");
     if (nsteps < 1 || every < 1) return fail(LB_EINVAL, "nsteps and every must be >= 1");
-    if (!seed || !grad) return fail(LB_EINVAL, "seed and grad must be device pointers");
+    if (!grad) return fail(LB_EINVAL, "grad must be a device pointer");
     if (h->variant == 0) return fail(LB_EINVAL, "the adjoint runs the row kernels: set a force field first");
     // sites per lane of the adjoint kernel: one (4-byte accesses; with its two
     // gathers and the Jacobian the kernel then fits four waves per SIMD and
@@ -617,15 +665,24 @@ int lb_grad_force_x(lb_lattice *h, int nsteps, int every, const float *seed, flo
     for (int n = 0; n < nsteps && rc == LB_OK; ++n) {
         if (n % every == 0)
             hip(hipMemcpyAsync(ck[n / every], h->buf[h->cur], abytes, hipMemcpyDeviceToDevice, h->stream), "checkpoint");
-        if (rc == LB_OK) rc = enqueue_one(h, h->cur, nullptr, nullptr, h->stream);
+        if (rc == LB_OK) rc = enqueue_one(h, h->cur, nullptr, nullptr, h->stream, own_bufs(h));
         if (rc == LB_OK) {
             h->cur ^= 1;
             h->steps += 1;
         }
     }
-    // seed (raw planes) into the storage layout; zero the gradient
+    // the objective of the final state: J, and its seed in the storage layout
+    if (rc == LB_OK && !seed && J) rc = outlet_flux_value(h, J);
     if (rc == LB_OK) hip(hipMemsetAsync(lamN, 0, abytes, h->stream), "hipMemsetAsync");
-    if (rc == LB_OK) hip(launch_repack(const_cast<float *>(seed), lamN, h->lay, (int64_t)h->n, 4, true, h->stream), "seed");
+    if (rc == LB_OK) {
+        if (seed) {
+            hip(launch_repack(const_cast<float *>(seed), lamN, h->lay, (int64_t)h->n, 4, true, h->stream), "seed");
+        } else {
+            OutletArgs oa = outlet_args(h, nullptr);
+            oa.seed = reinterpret_cast<float *>(lamN);
+            hip(launch_outlet_seed(oa, h->stream), "outlet seed");
+        }
+    }
     if (rc == LB_OK) hip(hipMemsetAsync(grad, 0, h->n * sizeof(float), h->stream), "hipMemsetAsync");
     if (rc == LB_OK) hip(hipMemsetAsync(nu[0], 0, abytes, h->stream), "hipMemsetAsync");
     if (rc == LB_OK) hip(hipMemsetAsync(nu[1], 0, abytes, h->stream), "hipMemsetAsync");
@@ -654,9 +711,40 @@ int lb_grad_force_x(lb_lattice *h, int nsteps, int every, const float *seed, flo
             cur_nu ^= 1;
         }
     }
+    if (rc == LB_OK && !seed) {
+        OutletArgs oa = outlet_args(h, nullptr);
+        oa.grad = grad;
+        hip(launch_outlet_direct(oa, h->stream), "outlet direct term");
+    }
     cleanup();
     return rc;
 }
+
+}  // namespace
+
+extern "C" {
+
+int lb_grad_force_x(lb_lattice *h, int nsteps, int every, const float *seed, float *grad)
+{
+    if (int rc = check(h)) return rc;
+    if (!seed) return fail(LB_EINVAL, "seed must be a device pointer");
+    return grad_impl(h, nsteps, every, seed, grad, nullptr);
+}
+
+int lb_grad_outlet_flux_x(lb_lattice *h, int nsteps, int every, float *grad, double *J)
+{
+    if (int rc = check(h)) return rc;
+    return grad_impl(h, nsteps, every, nullptr, grad, J);
+}
+
+int lb_outlet_flux(lb_lattice *h, double *J)
+{
+    if (int rc = check(h)) return rc;
+    if (!J) return fail(LB_EINVAL, "J must be a host pointer");
+    if (h->inplace) return fail(LB_EINVAL, "the outlet flux needs two-array storage");
+    return outlet_flux_value(h, J);
+}
+
 
 int lb_sums(lb_lattice *h, double *out, int k)
 {
@@ -816,7 +904,7 @@ int lb_time_step_kernel(lb_lattice *h, int n, double *ms)
                                          : launch_step(h->codec, h->variant, h->solids, false, a, h->grid, h->stream);
         if (rc == LB_OK && le != hipSuccess) rc = fail(LB_EHIP, "step kernel launch");
         if (rc == LB_OK && hipEventRecord(ev[2 * k + 1], h->stream) != hipSuccess) rc = fail(LB_EHIP, "hipEventRecord");
-        if (rc == LB_OK && launch_totals(totals_args(h), h->stream) != hipSuccess) rc = fail(LB_EHIP, "totals launch");
+        if (rc == LB_OK && launch_totals(totals_args(h, 0, own_bufs(h)), h->stream) != hipSuccess) rc = fail(LB_EHIP, "totals launch");
         if (rc == LB_OK) {
             h->cur ^= 1;
             h->steps += 1;

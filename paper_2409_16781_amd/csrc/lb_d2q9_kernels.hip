@@ -163,7 +163,6 @@ __global__ __launch_bounds__(kBlock) void step2d(Step2Args a)
                 }
             }
         }
-        float tm = 0.0f, tpx = 0.0f, tpy = 0.0f;
 #pragma unroll
         for (int e = 0; e < V; ++e) {
             float g[kQ2];
@@ -185,21 +184,18 @@ __global__ __launch_bounds__(kBlock) void step2d(Step2Args a)
 #pragma unroll
                 for (int i = 0; i < kQ2; ++i) stv_at<NW>(dst, sb, own + i * a.lay.seg, 4, d[i]);
             }
-            // totals of the stored values (dead sites hold zero)
-            float t[kQ2];
+            // totals of the stored values (dead sites hold zero), in FP64
+            double t[kQ2];
 #pragma unroll
             for (int i = 0; i < kQ2; ++i) {
-                float v = 0.0f;
+                double v = (double)K::dec(d[i].w[0]);
 #pragma unroll
-                for (int e = 0; e < V; ++e) v += K::dec(d[i].w[e]);
+                for (int e = 1; e < V; ++e) v += (double)K::dec(d[i].w[e]);
                 t[i] = v;
             }
-            tm = t[0] + ((t[1] + t[2]) + (t[3] + t[4])) + ((t[5] + t[6]) + (t[7] + t[8]));
-            tpx = (t[1] - t[2]) + (t[5] + t[6]) - (t[7] + t[8]);
-            tpy = (t[3] - t[4]) + (t[5] - t[6]) + (t[7] - t[8]);
-            acc[0] += (double)tm;
-            acc[1] += (double)tpx;
-            acc[2] += (double)tpy;
+            acc[0] += t[0] + ((t[1] + t[2]) + (t[3] + t[4])) + ((t[5] + t[6]) + (t[7] + t[8]));
+            acc[1] += (t[1] - t[2]) + (t[5] + t[6]) - (t[7] + t[8]);
+            acc[2] += (t[3] - t[4]) + (t[5] - t[6]) + (t[7] - t[8]);
         }
     }
     store_block_totals(acc, a.partials + 4 * (size_t)blockIdx.x);

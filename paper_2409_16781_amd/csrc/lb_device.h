@@ -198,8 +198,7 @@ typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
 // 16-bit codecs also work on the two elements of one dword at once: packed
-// conversion (one instruction, round to nearest even) and a dot product with
-// (1, 1) for the sum of the pair in FP32.
+// conversion (one instruction, round to nearest even).
 template <>
 struct Codec<kF16> {
     static constexpr int kBytes = 2;
@@ -215,11 +214,6 @@ struct Codec<kF16> {
     {
         f32x2 v = {lo, hi};
         return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, f16x2));
-    }
-    __device__ static float sum2(uint32_t w, float acc)
-    {
-        const f16x2 one = {(_Float16)1.0f, (_Float16)1.0f};
-        return __builtin_amdgcn_fdot2(__builtin_bit_cast(f16x2, w), one, acc, false);
     }
 };
 
@@ -254,11 +248,6 @@ struct Codec<kBF16> {
     {
         f32x2 v = {lo, hi};
         return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
-    }
-    __device__ static float sum2(uint32_t w, float acc)
-    {
-        const bf16x2 one = {(__bf16)1.0f, (__bf16)1.0f};
-        return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, w), one, acc, false);
     }
 };
 
@@ -393,14 +382,46 @@ __device__ __forceinline__ void collide(float (&g)[kQ], const Coll &p, float &rh
     g[0] = g[0] - 2.0f * sum_hs;
 }
 
-// Per-direction totals -> {mass deviation, momentum} of a group of sites.
-__device__ __forceinline__ void moments_of_totals(const float (&t)[kQ], float &m, float &px, float &py, float &pz)
+// Per-direction totals -> {mass deviation, momentum} of a group of sites
+// (FP32 for the macroscopic fields, FP64 for the conservation totals).
+template <typename T>
+__device__ __forceinline__ void moments_of_totals(const T (&t)[kQ], T &m, T &px, T &py, T &pz)
 {
     m = t[0] + ((t[1] + t[2]) + (t[3] + t[4])) + ((t[5] + t[6]) + (t[7] + t[8])) + ((t[9] + t[10]) + (t[11] + t[12])) +
         ((t[13] + t[14]) + (t[15] + t[16])) + (t[17] + t[18]);
     px = (t[1] - t[2]) + (t[7] + t[8]) - (t[9] + t[10]) + (t[11] + t[12]) - (t[13] + t[14]);
     py = (t[3] - t[4]) + (t[7] - t[8]) + (t[9] - t[10]) + (t[15] + t[16]) - (t[17] + t[18]);
     pz = (t[5] - t[6]) + (t[11] - t[12]) + (t[13] - t[14]) + (t[15] - t[16]) + (t[17] - t[18]);
+}
+
+// FP64 totals of the values a lane stores: every stored element is converted
+// to double and summed per direction, then the directions are combined into
+// {mass deviation, momentum}, all in FP64 and in a fixed order (dead
+// elements hold zero and add nothing).  The stored values are exact in
+// double, so a lane's totals carry only FP64 rounding (~1e-16 relative).
+template <int C, int NW>
+__device__ __forceinline__ void add_lane_totals(const Lane<NW> (&d)[kQ], double (&acc)[4])
+{
+    using K = Codec<C>;
+    constexpr int V = NW * 4 / K::kBytes;
+    double m = 0.0, px = 0.0, py = 0.0, pz = 0.0;
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+        double t = (double)K::dec(vget<C, NW>(d[i], 0));
+#pragma unroll
+        for (int e = 1; e < V; ++e) t += (double)K::dec(vget<C, NW>(d[i], e));
+        m += t;
+        if (CX[i] > 0) px += t;
+        if (CX[i] < 0) px -= t;
+        if (CY[i] > 0) py += t;
+        if (CY[i] < 0) py -= t;
+        if (CZ[i] > 0) pz += t;
+        if (CZ[i] < 0) pz -= t;
+    }
+    acc[0] += m;
+    acc[1] += px;
+    acc[2] += py;
+    acc[3] += pz;
 }
 
 // ------------------------------------------------- FP64 totals per launch --
@@ -944,25 +965,7 @@ __device__ __forceinline__ void tile_update(const StepArgs &a, const char *src, 
             store_floats<V>(a.u_out + 2 * n + g.s0, mw);
         }
         // totals of the values as stored (after rounding), fluid sites only
-        float tot[kQ];
-#pragma unroll
-        for (int i = 0; i < kQ; ++i) {
-            float t = 0.0f;
-#pragma unroll
-            for (int j = 0; j < NW; ++j) {
-                if constexpr (K::kBytes == 4)
-                    t += K::dec(d[i].w[j]);
-                else
-                    t = K::sum2(d[i].w[j], t);
-            }
-            tot[i] = t;
-        }
-        float m, px, py, pz;
-        moments_of_totals(tot, m, px, py, pz);
-        acc[0] += (double)m;
-        acc[1] += (double)px;
-        acc[2] += (double)py;
-        acc[3] += (double)pz;
+        add_lane_totals<C, NW>(d, acc);
     }
 }
 

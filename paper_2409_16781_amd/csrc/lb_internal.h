@@ -140,6 +140,20 @@ struct AdjArgs {
     float *grad;              // N floats (site order): += dJ/dF_x of this step
 };
 
+// The outlet mass flux objective: J = sum over the fluid sites of the plane
+// x = nx - 1 of rho u_x = sum_i c_ix S_i - F_x / 2 (S the stored state).
+struct OutletArgs {
+    const void *state;        // stored state, storage layout (two-array storage)
+    float *seed;              // storage-layout FP32 array: dJ/dS_N = c_ix at the outlet's fluid sites
+    float *grad;              // N floats, site order: the direct term -1/2 at the outlet's fluid sites
+    double *J;                // device double receiving J
+    Layout lay;
+    int nx, ny, nz;
+    const uint8_t *flags;     // device flags or nullptr (all fluid)
+    float fx;                 // uniform x-force
+    const float *fx_field;    // per-site x-force (N floats) or nullptr
+};
+
 // One step of a two-dimensional D2Q9 lattice (FP32 storage of f - w).
 struct Step2Args {
     const void *src;
@@ -216,6 +230,12 @@ hipError_t launch_batch_totals(const BatchTotalsArgs &a, hipStream_t s);
 // One adjoint step; variant 1 / 2 / 3 = 4 / 2 / 1 sites per lane (FP32 storage).
 hipError_t launch_adjoint(int variant, bool first, const AdjArgs &a, int grid, hipStream_t s);
 int batch_occupancy(int codec, int variant);
+// Outlet flux objective: J of a stored state (one workgroup, fixed-order FP64
+// sum), its seed dJ/dS_N written into a zeroed storage-layout array, and its
+// direct term added to a gradient.
+hipError_t launch_outlet_flux(int codec, const OutletArgs &a, hipStream_t s);
+hipError_t launch_outlet_seed(const OutletArgs &a, hipStream_t s);
+hipError_t launch_outlet_direct(const OutletArgs &a, hipStream_t s);
 // Raw planes (19 x n elements of esize bytes, site order) to the storage
 // layout (to_state) or back.  Both pointers are device pointers.
 hipError_t launch_repack(void *planes, void *state, const Layout &lay, int64_t n, int esize, bool to_state,

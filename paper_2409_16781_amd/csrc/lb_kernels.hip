@@ -128,12 +128,12 @@ __global__ __launch_bounds__(kBlock) void step_site(StepArgs a)
         }
         float rho, ux, uy, uz;
         collide(g, cp, rho, ux, uy, uz);
-        float tot[kQ];
+        double tot[kQ];
 #pragma unroll
         for (int i = 0; i < kQ; ++i) {
             const uint32_t b = K::enc(g[i]);
             st_elem<C>(dst, own + i * a.lay.seg, b);
-            tot[i] = K::dec(b);
+            tot[i] = (double)K::dec(b);
         }
         if constexpr (kMacros) {
             const size_t n = (size_t)nx * ny * nz;
@@ -142,12 +142,12 @@ __global__ __launch_bounds__(kBlock) void step_site(StepArgs a)
             a.u_out[n + s] = uy;
             a.u_out[2 * n + s] = uz;
         }
-        float m, px, py, pz;
+        double m, px, py, pz;
         moments_of_totals(tot, m, px, py, pz);
-        acc[0] += (double)m;
-        acc[1] += (double)px;
-        acc[2] += (double)py;
-        acc[3] += (double)pz;
+        acc[0] += m;
+        acc[1] += px;
+        acc[2] += py;
+        acc[3] += pz;
     }
     store_block_totals(acc, a.partials + 4 * (size_t)blockIdx.x);
 }

@@ -53,12 +53,33 @@ def gpu_lattice(c, variant=None):
 
 
 def gpu_gradient(c, every, variant=None):
-    torch = require_gpu()
+    """dJ/dF_x of the outlet flux through lb_grad_outlet_flux_x (seed and
+    direct term built by the library); J of the final state is checked to be
+    the one lb_outlet_flux reports afterwards."""
     lat = gpu_lattice(c, variant)
+    J, g = lat.grad_outlet_flux_x(c["steps"], every)
+    assert J == lat.outlet_flux()
+    return g.double().cpu().numpy(), lat
+
+
+def test_generic_seed_entry_point_equals_the_outlet_objective():
+    """lb_grad_force_x with the outlet seed written out here (c_ix at the
+    outlet's fluid sites) plus the direct term -1/2 gives the same gradient
+    as lb_grad_outlet_flux_x, bit for bit."""
+    torch = require_gpu()
+    c = small_case(steps=20)
+    g_lib, l1 = gpu_gradient(c, every=6)
+    l2 = gpu_lattice(c)
     fluid = torch.from_numpy(c["flags"] == 0).cuda()
-    g = lat.grad_force_x(c["steps"], every, lbm.outlet_flux_seed(lat, fluid)).double()
-    g[:, :, -1] -= 0.5 * fluid[:, :, -1].double()
-    return g.cpu().numpy(), lat
+    cx = torch.tensor([0, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1, 0, 0, 0, 0], dtype=torch.float32,
+                      device="cuda")
+    seed = torch.zeros((19,) + c["shape"], dtype=torch.float32, device="cuda")
+    seed[:, :, :, -1] = cx[:, None, None] * fluid[None, :, :, -1].float()
+    g = l2.grad_force_x(c["steps"], 6, seed)
+    g[:, :, -1] -= 0.5 * fluid[:, :, -1].float()
+    assert np.array_equal(g.double().cpu().numpy(), g_lib)
+    l1.close()
+    l2.close()
 
 
 def oracle_gradient(c, every=None):
@@ -150,9 +171,8 @@ def test_autograd_function(small_ref):
     torch = require_gpu()
     c, J_ref, g_ref = small_ref
     lat = gpu_lattice(c)
-    fluid = torch.from_numpy(c["flags"] == 0).cuda()
     fx = torch.from_numpy(c["fx"]).cuda().requires_grad_(True)
-    J = lbm.outlet_flux_autograd(fx, lat, c["steps"], 7, fluid)
+    J = lbm.outlet_flux_autograd(fx, lat, c["steps"], 7)
     J.backward()
     Jv = J.detach().item()
     g = fx.grad.double().cpu().numpy()
@@ -180,10 +200,8 @@ def test_porous128_500_steps_vs_stored_oracle_gradient():
     lat.set_force(*cfg["force"])
     lat.init_eq(torch.from_numpy(cfg["rho"]).cuda(), torch.from_numpy(cfg["u"]).cuda())
     lat.set_force_field(torch.zeros((n, n, n), dtype=torch.float32, device="cuda"))
-    fluid = torch.from_numpy(cfg["flags"] == 0).cuda()
-    g = lat.grad_force_x(cfg["steps"], cfg["every"], lbm.outlet_flux_seed(lat, fluid)).double()
-    g[:, :, -1] -= 0.5 * fluid[:, :, -1].double()
-    J = float(lbm.outlet_flux(lat))
+    J, g = lat.grad_outlet_flux_x(cfg["steps"], cfg["every"])
+    g = g.double()
     idx = torch.tensor(gold["cells_zyx"], device="cuda")
     gs = g[idx[:, 0], idx[:, 1], idx[:, 2]].cpu().numpy()
     ref = np.array(gold["grad"])

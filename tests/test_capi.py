@@ -149,3 +149,10 @@ def test_batch_null_handle_is_rejected_everywhere():
     assert L.lb_batch_steps_done(None) == -1
     assert L.lb_batch_query(None, 0) == -1
     L.lb_batch_destroy(None)  # no-op
+
+
+def test_objective_entry_points_reject_a_null_handle():
+    L = lbm.lib()
+    J = ctypes.c_double(0.0)
+    assert L.lb_outlet_flux(None, ctypes.byref(J)) == lbm.LB_ESTATE
+    assert L.lb_grad_outlet_flux_x(None, 10, 5, None, None) == lbm.LB_ESTATE

@@ -15,7 +15,8 @@
   FP16 storage and 1024^3 with FP32 storage, sampled sites after 4 steps.
 
 Bounds: relative L2 error of u <= 1e-5 (FP32 storage) and <= 2e-3 (FP16);
-BF16 storage is measured and reported against a sanity bound.
+BF16 storage is held to the same 2e-3 bound as FP16 and fails it (an expected
+failure, with the measured error).
 """
 import json
 import math
@@ -27,12 +28,12 @@ import pytest
 import oracle
 import paper_2409_16781_amd as lbm
 from paper_2409_16781_amd import inputs
-from gpu_util import require_gpu, say
+from gpu_util import bf16_bound, require_gpu, say
 
 pytestmark = pytest.mark.gpu
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-TOL = {"f32": 1e-5, "f16": 2e-3, "bf16": 5e-2}
+TOL = {"f32": 1e-5, "f16": 2e-3, "bf16": 2e-3}
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -77,6 +78,8 @@ def test_tgv512_1000_steps_whole_field(tgv512_ref, codec):
     err = rel_l2(u_g[:, 0].double().cpu().numpy(), c["u_ref"])
     drift = abs(sums[-1, 0] - sums[0, 0]) / sums[0, 0]
     say(f"  rel-L2(u) = {err:.3e} over all {n}^3 sites; mass drift over {c['steps']} steps {drift:.2e}")
+    if codec == "bf16":
+        bf16_bound(err)
     assert err <= TOL[codec]
     lat.close()
     torch.cuda.empty_cache()
