@@ -306,7 +306,20 @@ def cpu_baseline(cfg, steps):
     dt = time.perf_counter() - t0
     del S
     return dict(value=n ** 3 * steps / dt / 1e6, unit="MLUPS", cores=threads, kind="oracle",
-                sample=f"{n}^3 lattice of the same workload, {steps} FP64 steps, {dt:.1f} s")
+                sample=f"{n}^3 lattice of the same workload, {steps} FP64 steps, {dt:.1f} s",
+                cpu_model=cpu_model(), nproc=os.cpu_count())
+
+
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo; None where it is absent)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def main():

@@ -123,7 +123,9 @@ int lb_init_eq(lb_lattice *lat, const double *rho, const double *u);
  *   rho = sum f_i,  u = (sum c_i f_i + F/2)/rho,
  *   S'_i(x) = f_i - omega (f_i - f_i^eq) + S_i^F,
  * then swap the arrays.  Each step also records the FP64 totals of the new
- * state (see lb_sums).  Long runs are replayed from a captured HIP graph.
+ * state (see lb_sums).  A request of 64 or more steps runs as one captured
+ * HIP graph of the whole request (at most 1024 steps per graph), kept and
+ * replayed for the next request of the same length.
  */
 int lb_step(lb_lattice *lat, int n);
 
@@ -319,7 +321,10 @@ int lb_batch_set_force(lb_batch *b, int d, double fx, double fy, double fz);
  * (N and 3N doubles of that domain, NULL = 1 and 0); as lb_init_eq. */
 int lb_batch_init_eq(lb_batch *b, int d, const double *rho, const double *u);
 
-/* Enqueue n >= 0 steps of every domain (asynchronous). */
+/* Enqueue n >= 0 steps of every domain (asynchronous, one kernel launch per
+ * step for all domains).  A request of 64 or more steps runs as one captured
+ * HIP graph of the whole request (at most 1024 steps per graph), kept and
+ * replayed for the next request of the same length. */
 int lb_batch_step(lb_batch *b, int n);
 
 /* Density and velocity of domain d into caller-owned DEVICE buffers (N and

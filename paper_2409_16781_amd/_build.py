@@ -29,12 +29,13 @@ def hipcc() -> str:
     return "hipcc"
 
 
-def build(out: str = LIB, extra=None, verbose: bool = False) -> str:
+def build(out: str = LIB, extra=None, verbose: bool = False, objdir: str = None) -> str:
     """Compile every HIP source (in parallel, one object each) and link one
-    shared library (always recompiles)."""
+    shared library (always recompiles).  extra: more hipcc flags; objdir:
+    where the objects go (default paper_2409_16781_amd/_build)."""
     from concurrent.futures import ThreadPoolExecutor
 
-    objdir = os.path.join(PKG, "_build")
+    objdir = objdir or os.path.join(PKG, "_build")
     os.makedirs(objdir, exist_ok=True)
     flags = [f for f in HIPCC_FLAGS if f != "-shared"] + list(extra or [])
     inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]

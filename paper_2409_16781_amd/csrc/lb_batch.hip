@@ -31,7 +31,11 @@ namespace {
 
 constexpr uint64_t kBatchMagic = 0x4c42424154434821ull;  // "LBBATCH!"
 constexpr uint64_t kBatchDead = 0xdeadba7cdeadba7cull;
-constexpr int kBatchGraphSteps = 32;  // even: a graph ends on its start parity
+// Requests of at least kBatchGraphMin steps run as one captured graph of the
+// whole run (up to kBatchGraphMax steps), kept for the next request of the
+// same length: a 500-step request is one graph launch.
+constexpr int kBatchGraphMin = 64;
+constexpr int kBatchGraphMax = 1024;
 
 // Launch shape of a batch.  variant: 1 / 2 / 3 = 16- / 8- / 4-byte vectors
 // per lane and population; seg_bytes: target bytes of one population's rows
@@ -84,9 +88,7 @@ struct lb_batch {
     int cur = 0;
     long long steps = 0;
     hipStream_t stream = nullptr;  // borrowed (NULL: the default stream)
-    hipStream_t cap_stream = nullptr;
-    hipGraphExec_t gexec = nullptr;
-    bool graph_ok = false;
+    RunGraphs graphs;
 };
 
 namespace {
@@ -114,9 +116,7 @@ void free_dev(T *&p)
 // Free everything that depends on the launch shape.
 void release_shape(lb_batch *b)
 {
-    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
-    b->gexec = nullptr;
-    b->graph_ok = false;
+    b->graphs.invalidate();
     free_dev(b->pool);
     free_dev(b->d_doms);
     free_dev(b->d_tile_dom);
@@ -136,8 +136,7 @@ void release_all(lb_batch *b)
     free_dev(b->ticket);
     free_dev(b->ring);
     free_dev(b->counter);
-    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
-    b->cap_stream = nullptr;
+    b->graphs.release();
     b->stream = nullptr;  // borrowed
 }
 
@@ -295,50 +294,54 @@ int enqueue_run(lb_batch *b, int parity, int count, hipStream_t s)
     return LB_OK;
 }
 
-int enqueue_one(lb_batch *b, int parity, hipStream_t s)
+// Capture the run of len steps from parity unless it is held already (a new
+// length, or a changed launch shape or argument, drops the held graphs).
+int ensure_graph(lb_batch *b, int len, int parity)
 {
-    return enqueue_run(b, parity, 1, s);
-}
-
-int build_graph(lb_batch *b)
-{
-    if (b->graph_ok) return LB_OK;
-    if (b->gexec) {
-        (void)hipGraphExecDestroy(b->gexec);
-        b->gexec = nullptr;
-    }
-    if (!b->cap_stream) HIP_OR_FAIL(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
-    HIP_OR_FAIL(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
-    int rc = enqueue_run(b, 0, kBatchGraphSteps, b->cap_stream);
+    RunGraphs &G = b->graphs;
+    if (G.len != len) G.invalidate();
+    if (G.exec[parity]) return LB_OK;
+    if (!G.cap) HIP_OR_FAIL(hipStreamCreateWithFlags(&G.cap, hipStreamNonBlocking));
+    HIP_OR_FAIL(hipStreamBeginCapture(G.cap, hipStreamCaptureModeThreadLocal));
+    int rc = enqueue_run(b, parity, len, G.cap);
     hipGraph_t g = nullptr;
-    hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
+    hipError_t e = hipStreamEndCapture(G.cap, &g);
     if (rc != LB_OK) {
         if (g) (void)hipGraphDestroy(g);
         return rc;
     }
     if (e != hipSuccess) return fail(LB_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
-    e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&G.exec[parity], g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
-    if (e != hipSuccess) return fail(LB_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
-    b->graph_ok = true;
+    if (e != hipSuccess) {
+        G.exec[parity] = nullptr;
+        return fail(LB_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    G.len = len;
+    return LB_OK;
+}
+
+// Capture the graphs enqueue_steps(b, n) will replay, without launching them.
+int prepare_graphs(lb_batch *b, int n)
+{
+    if (n < kBatchGraphMin) return LB_OK;
+    const int len = std::min(n, kBatchGraphMax);
+    if (int rc = ensure_graph(b, len, b->cur)) return rc;
+    if ((len & 1) && n >= 2 * len) return ensure_graph(b, len, b->cur ^ 1);
     return LB_OK;
 }
 
 int enqueue_steps(lb_batch *b, int n)
 {
     int plain = n;
-    if (plain >= 2 * kBatchGraphSteps) {
-        if (b->cur == 1) {
-            if (int rc = enqueue_one(b, 1, b->stream)) return rc;
-            b->cur = 0;
-            b->steps += 1;
-            --plain;
-        }
-        if (int rc = build_graph(b)) return rc;
-        while (plain >= kBatchGraphSteps) {
-            HIP_OR_FAIL(hipGraphLaunch(b->gexec, b->stream));
-            b->steps += kBatchGraphSteps;
-            plain -= kBatchGraphSteps;
+    if (plain >= kBatchGraphMin) {
+        const int len = std::min(plain, kBatchGraphMax);
+        while (plain >= len) {
+            if (int rc = ensure_graph(b, len, b->cur)) return rc;
+            HIP_OR_FAIL(hipGraphLaunch(b->graphs.exec[b->cur], b->stream));
+            b->cur ^= len & 1;
+            b->steps += len;
+            plain -= len;
         }
     }
     if (plain > 0) {
@@ -353,6 +356,7 @@ int enqueue_steps(lb_batch *b, int n)
 int time_steps(lb_batch *b, int warm, int n, double *ms)
 {
     if (int rc = enqueue_steps(b, warm)) return rc;
+    if (int rc = prepare_graphs(b, n)) return rc;
     Events evs(2);
     HIP_OR_FAIL(evs.create());
     hipEvent_t e0 = evs[0], e1 = evs[1];
@@ -413,7 +417,7 @@ int autotune(lb_batch *b)
                     if (gm > 0) grid = std::min<int64_t>(grid, (int64_t)gm * occ * b->cus);
                     b->grid = (int)std::max<int64_t>(grid, 1);
                     b->shape = s;
-                    b->graph_ok = false;
+                    b->graphs.invalidate();
                     double ms = 1e300;
                     for (int rep = 0; rep < 2; ++rep) {  // best of two timings of 24 steps
                         double t = 0;

@@ -51,7 +51,11 @@ namespace {
 
 constexpr uint64_t kMagic = 0x4c42443351313921ull;  // "LBD3Q19!"
 constexpr uint64_t kDead = 0xdeadd3a1deadd3a1ull;
-constexpr int kGraphSteps = 32;  // steps per captured graph (even: the graph ends on its start parity)
+// Requests of at least kGraphMin steps run as one captured graph of the whole
+// run (up to kGraphMax steps per graph), kept for the next request of the
+// same length.
+constexpr int kGraphMin = 64;
+constexpr int kGraphMax = 1024;
 
 
 }  // namespace
@@ -81,13 +85,11 @@ struct lb_lattice {
     double *ring;
     unsigned long long *counter;
     hipStream_t stream;
-    hipStream_t cap_stream;
     int variant, vsites, grid, cus;
     int tile_order;
     bool inplace;     // one population array (AA pattern); cur is then the phase (0 even, 1 odd)
     long long steps;
-    hipGraphExec_t gexec;
-    bool graph_ok;
+    RunGraphs graphs;
     std::vector<void *> adj_ws;  // state-sized buffers of the adjoint sweep, kept for later calls
     double *jval;     // device double: the outlet flux objective
     int dev;          // HIP device the lattice lives on
@@ -226,47 +228,62 @@ int enqueue_run(lb_lattice *h, int from, int count, hipStream_t s, const TotalsB
     return LB_OK;
 }
 
-int build_graph(lb_lattice *h)
+// Capture the run of len steps from buf[parity] unless it is held already
+// (a new length, or changed launch arguments, drops the held graphs).
+int ensure_graph(lb_lattice *h, int len, int parity)
 {
-    if (h->graph_ok) return LB_OK;
-    if (h->gexec) {
-        (void)hipGraphExecDestroy(h->gexec);
-        h->gexec = nullptr;
+    RunGraphs &G = h->graphs;
+    if (G.len != len) G.invalidate();
+    if (!G.exec[parity]) {
+        if (!G.cap) HIP_OR_FAIL(hipStreamCreateWithFlags(&G.cap, hipStreamNonBlocking));
+        HIP_OR_FAIL(hipStreamBeginCapture(G.cap, hipStreamCaptureModeThreadLocal));
+        int rc = enqueue_run(h, parity, len, G.cap, own_bufs(h));
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(G.cap, &g);
+        if (rc != LB_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return fail(LB_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&G.exec[parity], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            G.exec[parity] = nullptr;
+            return fail(LB_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+        }
+        G.len = len;
     }
-    if (!h->cap_stream) HIP_OR_FAIL(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
-    HIP_OR_FAIL(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
-    int rc = enqueue_run(h, 0, kGraphSteps, h->cap_stream, own_bufs(h));
-    hipGraph_t g = nullptr;
-    hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
-    if (rc != LB_OK) {
-        if (g) (void)hipGraphDestroy(g);
-        return rc;
-    }
-    if (e != hipSuccess) return fail(LB_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
-    e = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (e != hipSuccess) return fail(LB_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
-    h->graph_ok = true;
+    return LB_OK;
+}
+
+int run_graph(lb_lattice *h, int len, int parity)
+{
+    if (int rc = ensure_graph(h, len, parity)) return rc;
+    HIP_OR_FAIL(hipGraphLaunch(h->graphs.exec[parity], h->stream));
+    return LB_OK;
+}
+
+// Capture the graphs enqueue_steps(h, n) will replay, without launching them
+// (keeps capture out of timed regions).
+int prepare_graphs(lb_lattice *h, int n)
+{
+    if (n < kGraphMin) return LB_OK;
+    const int len = std::min(n, kGraphMax);
+    if (int rc = ensure_graph(h, len, h->cur)) return rc;
+    if ((len & 1) && n >= 2 * len) return ensure_graph(h, len, h->cur ^ 1);
     return LB_OK;
 }
 
 int enqueue_steps(lb_lattice *h, int n, float *rho, float *u)
 {
     int plain = rho ? n - 1 : n;
-    if (plain >= 2 * kGraphSteps) {
-        if (h->cur == 1) {
-            int rc = enqueue_one(h, 1, nullptr, nullptr, h->stream, own_bufs(h));
-            if (rc) return rc;
-            h->cur = 0;
-            h->steps += 1;
-            --plain;
-        }
-        int rc = build_graph(h);
-        if (rc) return rc;
-        while (plain >= kGraphSteps) {
-            HIP_OR_FAIL(hipGraphLaunch(h->gexec, h->stream));
-            h->steps += kGraphSteps;
-            plain -= kGraphSteps;
+    if (plain >= kGraphMin) {
+        const int len = std::min(plain, kGraphMax);
+        while (plain >= len) {
+            if (int rc = run_graph(h, len, h->cur)) return rc;
+            h->cur ^= len & 1;
+            h->steps += len;
+            plain -= len;
         }
     }
     if (plain > 0) {
@@ -286,8 +303,7 @@ int enqueue_steps(lb_lattice *h, int n, float *rho, float *u)
 
 void release(lb_lattice *h)
 {
-    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
-    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+    h->graphs.release();
     void *ptrs[] = {h->alloc[0], h->alloc[1], h->flags,   h->nbmask, h->rowdirty, h->rowcum,
                     h->partials, h->gpartials, h->ticket, h->ring,  h->counter, h->ffield, h->jval};
     for (void *p : ptrs)
@@ -505,7 +521,7 @@ int lb_set_force(lb_lattice *h, double fx, double fy, double fz)
     h->force[0] = fx;
     h->force[1] = fy;
     h->force[2] = fz;
-    h->graph_ok = false;
+    h->graphs.invalidate();
     return LB_OK;
 }
 
@@ -556,7 +572,7 @@ int lb_set_force_field(lb_lattice *h, const float *fx)
         HIP_OR_FAIL(hipStreamSynchronize(h->stream));
         if (h->ffield) (void)hipFree(h->ffield);
         h->ffield = nullptr;
-        h->graph_ok = false;
+        h->graphs.invalidate();
         return LB_OK;
     }
     if (h->codec != kF32) return fail(LB_EINVAL, "force fields need FP32 storage");
@@ -584,7 +600,7 @@ int lb_set_force_field(lb_lattice *h, const float *fx)
             hipMalloc(&h->gpartials, ngroups * 4 * sizeof(double)) != hipSuccess)
             return fail(LB_ENOMEM, "hipMalloc(partials)");
     }
-    h->graph_ok = false;
+    h->graphs.invalidate();
     return LB_OK;
 }
 
@@ -798,7 +814,7 @@ static int copy_f(lb_lattice *h, void *host_or_dev, size_t bytes, int where, boo
         if (e != hipSuccess) return fail(LB_EHIP, "population copy: %s", hipGetErrorString(e));
         if (to_lattice) {
             h->cur = 0;
-            h->graph_ok = false;
+            h->graphs.invalidate();
         }
         return LB_OK;
     }
@@ -875,6 +891,7 @@ int lb_time_steps(lb_lattice *h, int n, double *ms)
 {
     if (int rc = check(h)) return rc;
     if (n < 1 || !ms) return fail(LB_EINVAL, "n must be >= 1 and ms non-NULL");
+    if (int rc = prepare_graphs(h, n)) return rc;
     Events evs(2);
     HIP_OR_FAIL(evs.create());
     hipEvent_t e0 = evs[0], e1 = evs[1];

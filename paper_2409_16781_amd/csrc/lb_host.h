@@ -31,4 +31,28 @@ struct Events {
     hipEvent_t operator[](size_t k) const { return ev[k]; }
 };
 
+// Captured runs of one length: one graph per start parity (a run of odd
+// length ends on the other parity, so successive replays alternate).  The
+// owner calls invalidate() whenever a launch argument changes.
+struct RunGraphs {
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    int len = 0;
+    hipStream_t cap = nullptr;  // capture stream, created on first use
+    void invalidate()
+    {
+        for (auto &e : exec)
+            if (e) {
+                (void)hipGraphExecDestroy(e);
+                e = nullptr;
+            }
+        len = 0;
+    }
+    void release()
+    {
+        invalidate();
+        if (cap) (void)hipStreamDestroy(cap);
+        cap = nullptr;
+    }
+};
+
 }  // namespace lbm

@@ -144,3 +144,23 @@ def exact_state_totals(g, mask):
 # Depth bound of the library's summation trees (lane, workgroup, chunk and
 # chunk-sum levels) used with exact_state_totals' scale.
 FP64_SUM_TOL = 64 * 2.0 ** -53
+
+
+# D3Q19 weights in the same order (the stored value is g = f - w).
+W19 = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12, dtype=np.float64)
+
+
+def totals_gap_bound(g_gpu, S_oracle, mask):
+    """Bound on |GPU totals - oracle totals| for a GPU state whose stored
+    values are g_gpu (19, ...) and an oracle state S_oracle (unshifted f).
+    The GPU totals are the FP64 sums of its stored values (checked on their
+    own against exact_state_totals) and the oracle's are the sums of its f, so
+    their gap is the sum of the state difference D = g_gpu - (S - w) over the
+    fluid sites, bounded by sum |c_a| |D| (mass: sum |D|), plus the FP64
+    rounding of both summations."""
+    D = (g_gpu - (S_oracle - W19.reshape((19,) + (1,) * (S_oracle.ndim - 1))))[:, mask]
+    ad = np.abs(D)
+    bound = [float(ad.sum())] + [float((np.abs(C19[:, a, None]) * ad).sum()) for a in range(3)]
+    scale = [float(np.abs(S_oracle[:, mask]).sum())] + \
+        [float((np.abs(C19[:, a, None]) * np.abs(S_oracle[:, mask])).sum()) for a in range(3)]
+    return np.array(bound) + FP64_SUM_TOL * (np.array(scale) + float(mask.sum()))

@@ -18,7 +18,8 @@ import pytest
 import oracle
 import paper_2409_16781_amd as lbm
 from paper_2409_16781_amd import inputs
-from gpu_util import FP64_SUM_TOL, decode_raw, exact_state_totals, fluid_mask, oracle_run, rel_l2_u, require_gpu, say
+from gpu_util import (FP64_SUM_TOL, decode_raw, exact_state_totals, fluid_mask, oracle_run, rel_l2_u, require_gpu, say,
+                      totals_gap_bound)
 
 pytestmark = pytest.mark.gpu
 
@@ -160,29 +161,33 @@ def test_totals_per_domain_match_oracle(mixed_ref):
     for k, (d, (_, _, S)) in enumerate(zip(doms, refs)):
         tot = b.sums(k, 1)[0]
         ref = oracle.sums(S, d["flags"])
-        say(f"  domain {k}: totals - oracle totals = {tot - ref}")
-        # the totals are FP64 sums; they differ from the FP64 oracle's by the
-        # rounding of the FP32-stored state only
-        assert abs(tot[0] - ref[0]) <= 1e-6, (k, tot, ref)
-        for c in (1, 2, 3):
-            assert abs(tot[c] - ref[c]) <= 1e-7 * max(1.0, abs(ref[c])) + 1e-9, (k, c, tot, ref)
-        # and they are the FP64 sums of the stored state itself
-        exact, scale = exact_state_totals(decode_raw(b.get_f(k), "f32"), fluid_mask(d))
+        g = decode_raw(b.get_f(k), "f32")
+        m = fluid_mask(d)
+        bound = totals_gap_bound(g, S, m)
+        say(f"  domain {k}: totals - oracle totals = {tot - ref}, bound {bound}")
+        # the totals are the FP64 sums of the stored state itself ...
+        exact, scale = exact_state_totals(g, m)
         assert np.all(np.abs(tot - exact) <= FP64_SUM_TOL * scale), (k, tot, exact, scale)
+        # ... so they differ from the FP64 oracle's by the summed difference of
+        # the FP32 state from the oracle's state only
+        assert np.all(np.abs(tot - ref) <= bound), (k, tot - ref, bound)
     b.close()
 
 
 def test_graph_replay_equals_eager_steps():
     doms = mixed_domains()
     b1 = make_batch(doms, "f32")
-    b1.step(70)  # 70 >= 64: captured-graph path
+    b1.step(70)  # 70 >= 64: one captured graph of the whole run
+    b1.step(65)  # odd runs: captured from each parity
+    b1.step(65)
+    total = 200
     b2 = make_batch(doms, "f32")
-    for _ in range(70):
+    for _ in range(total):
         b2.step(1)
     for k in range(len(doms)):
         assert np.array_equal(b1.get_f(k), b2.get_f(k)), k
         # every domain's whole ring of per-step totals, chained runs vs single steps
-        assert np.array_equal(b1.sums(k, 70), b2.sums(k, 70)), k
+        assert np.array_equal(b1.sums(k, total), b2.sums(k, total)), k
     b1.close()
     b2.close()
 
