@@ -130,6 +130,24 @@ int lb_init_eq(lb_lattice *lat, const double *rho, const double *u);
 int lb_step(lb_lattice *lat, int n);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same n
+ * steps as lb_step, with the same results (state and totals bit for bit), but
+ * the call allocates nothing.  The totals' scratch (the reduce's arrival
+ * ticket and the per-workgroup FP64 partials) lives in a file-scope device
+ * array of the library, 8 MiB + 64 KiB per device, held until the process
+ * ends; each step is an ordinary kernel launch on the lattice stream (no
+ * graph is built, so a caller may capture the call into its own).
+ * Limit: 64 bytes per step workgroup plus 256 + 32 per 256 workgroups; a
+ * 512^3 lattice at 4 sites per lane (131072 workgroups) fits, lattices that
+ * need more are rejected with LB_EINVAL and the sizes in lb_last_error().  All calls on one device
+ * share the one array, which keeps the last call's contents: calls that
+ * overlap on one device (other streams, other threads) race and must not be
+ * issued.  Call with the lattice's device current.
+ */
+int lb_step_noalloc(lb_lattice *lat, int n);
+
+/*
  * As lb_step with n >= 1, and the last step also writes the density and
  * velocity it computes (the pre-collision moments of that step, u including
  * the half-force shift) into caller-owned device arrays rho (N floats) and u

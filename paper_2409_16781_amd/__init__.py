@@ -35,6 +35,7 @@ _SIGNATURES = {
     "lb_set_force": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
     "lb_init_eq": (ctypes.c_int, [_P, _P, _P]),
     "lb_step": (ctypes.c_int, [_P, ctypes.c_int]),
+    "lb_step_noalloc": (ctypes.c_int, [_P, ctypes.c_int]),
     "lb_step_macros": (ctypes.c_int, [_P, ctypes.c_int, _P, _P]),
     "lb_macros": (ctypes.c_int, [_P, _P, _P]),
     "lb_sums": (ctypes.c_int, [_P, _P, ctypes.c_int]),
@@ -178,6 +179,11 @@ class Lattice:
 
     def step(self, n: int = 1):
         _check(lib().lb_step(self._h, int(n)), "lb_step")
+
+    def step_noalloc(self, n: int = 1):
+        """As step(), with no device allocation in the call (the totals'
+        scratch is the library's static per-device array)."""
+        _check(lib().lb_step_noalloc(self._h, int(n)), "lb_step_noalloc")
 
     def step_macros(self, n: int = 1):
         """n steps; the last one also returns its (rho, u) as float32 tensors."""

@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -22,6 +23,14 @@
 #include "lb_internal.h"
 
 using namespace lbm;
+
+// Scratch of lb_step_noalloc: the totals reduce's arrival ticket, the reduce
+// workgroups' partials and the two buffers of step-workgroup partials, in one
+// file-scope device array instead of the lattice's own allocations.  Every
+// device holds its own copy at its own address; host code uses only that
+// address (scratch_base), never the array's name.
+constexpr size_t kScratchBytes = ((size_t)8 << 20) + ((size_t)64 << 10);  // 8 MiB + 64 KiB
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace lbm {
 
@@ -170,6 +179,54 @@ struct TotalsBufs {
 };
 
 TotalsBufs own_bufs(const lb_lattice *h) { return TotalsBufs{h->partials, h->gpartials, h->ticket}; }
+
+// ---- the scratch array's address per device (resolved once per device, with
+// that device current, when the first lattice is created on it)
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_base[kMaxDevices];
+
+int resolve_scratch(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) return fail(LB_EHIP, "device %d beyond the library's %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_base[dev]) return LB_OK;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr)
+        return fail(LB_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_base[dev] = static_cast<unsigned char *>(p);
+    return LB_OK;
+}
+
+unsigned char *scratch_base(int dev)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return (dev >= 0 && dev < kMaxDevices) ? g_scratch_base[dev] : nullptr;
+}
+
+// Scratch layout for lattice h: ticket (one 256-byte slot), the reduce
+// workgroups' partials (4 doubles each, rounded up to 256 bytes), then two
+// buffers of 4 doubles per step workgroup.
+size_t scratch_gpart_bytes(const lb_lattice *h)
+{
+    const size_t ngroups = ((size_t)h->grid + kRedChunk - 1) / kRedChunk;
+    return (ngroups * 4 * sizeof(double) + 255) & ~(size_t)255;
+}
+
+size_t scratch_need(const lb_lattice *h)
+{
+    return 256 + scratch_gpart_bytes(h) + (size_t)h->grid * 8 * sizeof(double);
+}
+
+TotalsBufs scratch_bufs(const lb_lattice *h, unsigned char *base)
+{
+    TotalsBufs tb;
+    tb.ticket = reinterpret_cast<unsigned int *>(base);
+    tb.gpartials = reinterpret_cast<double *>(base + 256);
+    tb.partials = reinterpret_cast<double *>(base + 256 + scratch_gpart_bytes(h));
+    return tb;
+}
 
 // Totals of the step whose workgroup partials are in buffer buf (0 or 1).
 TotalsArgs totals_args(const lb_lattice *h, int buf, const TotalsBufs &tb)
@@ -425,6 +482,10 @@ int create_impl(lb_lattice **out, int nx, int ny, int nz, double tau, const uint
     }
     h->cus = prop.multiProcessorCount;
     h->dev = dev;
+    if (int rc = resolve_scratch(dev)) {
+        delete h;
+        return rc;
+    }
     // One workgroup per tile of kBlock lanes.  LB_WG_PER_CU caps the grid at
     // that many workgroups per compute unit (each then loops over tiles).
     const uint64_t tiles = (n / h->vsites + kBlock - 1) / kBlock;
@@ -548,6 +609,28 @@ int lb_step(lb_lattice *h, int n)
     if (int rc = check(h)) return rc;
     if (n < 0) return fail(LB_EINVAL, "step count must be >= 0 (got %d)", n);
     return enqueue_steps(h, n, nullptr, nullptr);
+}
+
+int lb_step_noalloc(lb_lattice *h, int n)
+{
+    if (int rc = check(h)) return rc;
+    if (n < 0) return fail(LB_EINVAL, "step count must be >= 0 (got %d)", n);
+    const size_t need = scratch_need(h);
+    if (need > kScratchBytes)
+        return fail(LB_EINVAL,
+                    "lb_step_noalloc: the totals of this lattice need %zu bytes of scratch (%d step workgroups); "
+                    "the library's static scratch holds %zu bytes",
+                    need, h->grid, kScratchBytes);
+    if (n == 0) return LB_OK;
+    unsigned char *base = scratch_base(h->dev);
+    if (!base) return fail(LB_ESTATE, "scratch address of device %d not resolved", h->dev);
+    const TotalsBufs tb = scratch_bufs(h, base);
+    // the ticket must start at zero: a kernel, not a memset, clears it
+    HIP_OR_FAIL(launch_zero_words(tb.ticket, 1, h->stream));
+    if (int rc = enqueue_run(h, h->cur, n, h->stream, tb)) return rc;
+    h->cur ^= n & 1;
+    h->steps += n;
+    return LB_OK;
 }
 
 int lb_step_macros(lb_lattice *h, int n, float *rho, float *u)

@@ -212,6 +212,7 @@ hipError_t launch_masks(const uint8_t *flags, int nx, int ny, int nz, int pitch,
                         uint32_t *rowcum, hipStream_t s);
 hipError_t launch_zero_solid_macros(const uint8_t *flags, int n, float *rho, float *u, hipStream_t s);
 hipError_t launch_copy(const void *src, void *dst, uint64_t bytes, hipStream_t s);
+hipError_t launch_zero_words(unsigned int *p, int n, hipStream_t s);  // n words set to 0 by a kernel
 int step_occupancy(int codec, int variant, bool solids, bool macros);  // workgroups per CU
 
 // Host helpers of the runtime files.  fail() records the message that

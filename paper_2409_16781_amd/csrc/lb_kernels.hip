@@ -27,6 +27,14 @@
 namespace lbm {
 namespace {
 
+// Sets n words to zero (a kernel rather than a memset, so that a caller may
+// capture it into a graph).
+__global__ __launch_bounds__(kBlock) void zero_words(unsigned int *p, int n)
+{
+    const int i = blockIdx.x * kBlock + (int)threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
 // Workgroup g sums partials [g * kRedChunk, (g + 1) * kRedChunk) into
 // gpartials[g]; the last workgroup to finish sums the gpartials in order and
 // appends {mass, momentum} of the step to the ring.
@@ -537,6 +545,13 @@ hipError_t launch_masks(const uint8_t *flags, int nx, int ny, int nz, int pitch,
 hipError_t launch_zero_solid_macros(const uint8_t *flags, int n, float *rho, float *u, hipStream_t s)
 {
     zero_solid_macros<<<grid_for((uint64_t)n), kBlock, 0, s>>>(flags, n, rho, u);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_words(unsigned int *p, int n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    zero_words<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(p, n);
     return hipGetLastError();
 }
 

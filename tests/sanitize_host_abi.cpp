@@ -45,6 +45,7 @@ int main()
     lb2d_destroy(nullptr);
     double sums[8];
     expect(lb_step(nullptr, 1) == LB_ESTATE, "lb_step(NULL)");
+    expect(lb_step_noalloc(nullptr, 1) == LB_ESTATE, "lb_step_noalloc(NULL)");
     expect(lb_sums(nullptr, sums, 1) == LB_ESTATE, "lb_sums(NULL)");
     expect(lb_macros(nullptr, nullptr, nullptr) == LB_ESTATE, "lb_macros(NULL)");
     expect(lb_batch_step(nullptr, 1) == LB_ESTATE, "lb_batch_step(NULL)");
@@ -65,6 +66,7 @@ int main()
         expect(lb_set_force(lat, 1e-5, 0.0, 0.0) == LB_OK, "set_force");
         expect(lb_init_eq(lat, nullptr, nullptr) == LB_OK, "init_eq");
         expect(lb_step(lat, 70) == LB_OK, "step");
+        expect(lb_step_noalloc(lat, 3) == LB_OK, "step_noalloc");
         expect(lb_sums(lat, sums, 2) == LB_OK, "sums");
         lb_destroy(lat);
         const int bd[6] = {8, 6, 4, 12, 5, 3};
