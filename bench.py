@@ -3,13 +3,16 @@
 
 Workload: 512^3 periodic lattice, Taylor-Green vortex (u0 = 0.01,
 k = 2 pi / 512) plus seeded uniform +-1e-3 noise on every velocity component,
-tau = 0.55, no body force; populations stored as FP32, FP16 or BF16 (shifted
-by the lattice weights), FP32 arithmetic, FP64 conservation totals every step.
+tau = 0.55, no body force; populations stored as FP32, FP16, BF16 or scaled
+16-bit fixed point (shifted by the lattice weights), FP32 arithmetic, FP64
+conservation totals every step.
 A step is one launch of the fused update over all 134,217,728 sites with the
 inputs already resident in HBM.
 
 Prints one JSON line: MLUPS of the FP32-storage path as ``value``, the
-16-bit-storage results beside it, the HBM roofline of the step kernel
+16-bit-storage results beside it, each codec's error against stored FP64
+oracle results of the same workload after 200 and 1000 steps (the
+equal-accuracy half of the metric), the HBM roofline of the step kernel
 (algorithmic bytes: 19 loads + 19 stores per site), a copy-kernel ceiling
 measured in the same run, and the FP64 oracle timed on the host cores on a
 bounded sample of the same workload.
@@ -37,7 +40,9 @@ def parse():
     p.add_argument("--steps", type=int, default=200)
     p.add_argument("--warmup", type=int, default=20)
     p.add_argument("--n", type=int, default=512, help="lattice edge (default 512)")
-    p.add_argument("--codecs", default="f32,f16,bf16")
+    p.add_argument("--codecs", default="f32,f16,bf16,s16")
+    p.add_argument("--no-accuracy", action="store_true",
+                   help="skip the 1000-step accuracy leg against the stored oracle results")
     p.add_argument("--cpu-steps", type=int, default=5, help="oracle steps in the CPU baseline sample")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
     p.add_argument("--reps", type=int, default=3, help="timed repetitions (median reported)")
@@ -93,7 +98,7 @@ def measured_traffic(codec, n):
 
 
 def bytes_per_site(codec):
-    return 19 * 2 * (4 if codec == "f32" else 2)
+    return 19 * 2 * (4 if codec == "f32" else 2)  # f16, bf16, s16: 2 bytes
 
 
 def run_codec(torch, lbm, cfg, codec, steps, warmup, reps):
@@ -139,6 +144,9 @@ def run_codec(torch, lbm, cfg, codec, steps, warmup, reps):
                frac_copy=gbs / copy_gbs, mass_drift_per_step=drift / max(1, len(sums) - 1),
                variant=lat.info["variant"], sites_per_thread=lat.info["sites_per_thread"],
                grid=lat.info["grid"], steps_done=lat.steps_done)
+    if codec == "s16":
+        res["exponents"] = [int(e) for e in lat.get_scales()]
+        res["widenings"] = lat.info["rescales"]
     lat.close()
     return res, u_out
 
@@ -294,6 +302,50 @@ def run_small(torch, lbm, reps, steps=0):
     return out
 
 
+GOLDEN_NOISE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden",
+                            "tgv512_noise_golden.npz")
+ACCURACY_BOUND = {"f32": 1e-5, "f16": 2e-3, "bf16": 2e-3, "s16": 2e-3}
+
+
+def accuracy_vs_oracle(torch, lbm, cfg, codecs):
+    """rel-L2 of u against stored FP64 oracle results of the same 512^3
+    workload (written by tests/golden/make_tgv512_noise_golden.py from the
+    oracle alone) at their seeded sample sites, after 200 and 1000 steps."""
+    n = cfg["shape"][0]
+    if n != 512 or not os.path.exists(GOLDEN_NOISE):
+        return None
+    with np.load(GOLDEN_NOISE) as z:
+        gold = {k: z[k] for k in z.files}
+    idx = torch.from_numpy(gold["sites_zyx"]).cuda()
+    out = {}
+    for codec in codecs:
+        lat = lbm.Lattice(n, n, n, cfg["tau"], codec=codec)
+        lat.init_eq(torch.from_numpy(cfg["rho"]).cuda(), torch.from_numpy(cfg["u"]).cuda())
+        torch.cuda.empty_cache()
+        res, done = {}, 0
+        for k in (200, 1000):
+            lat.step(k - done)
+            done = k
+            _, u = lat.macros()
+            ug = u[:, idx[:, 0], idx[:, 1], idx[:, 2]].T.double().cpu().numpy()
+            ref = gold[f"u_{k}"]
+            res[f"rel_l2_u_{k}"] = float(np.linalg.norm(ug - ref) / np.linalg.norm(ref))
+            del u
+        res["bound"] = ACCURACY_BOUND.get(codec)
+        res["meets_bound"] = bool(res["rel_l2_u_1000"] <= res["bound"])
+        if codec == "s16":
+            res["exponents"] = [int(e) for e in lat.get_scales()]
+            res["widenings"] = lat.info["rescales"]
+        lat.close()
+        torch.cuda.empty_cache()
+        out[codec] = res
+        log(f"[bench] accuracy {codec}: rel-L2(u) vs oracle {res['rel_l2_u_200']:.2e} (200 steps), "
+            f"{res['rel_l2_u_1000']:.2e} (1000 steps), bound {res['bound']:g}")
+    out["samples"] = int(len(gold["sites_zyx"]))
+    out["reference"] = "FP64 oracle, tests/golden/tgv512_noise_golden.npz"
+    return out
+
+
 def cpu_baseline(cfg, steps):
     """The FP64 oracle as it stands, on the host cores, for a few steps of the same lattice."""
     import oracle
@@ -386,6 +438,13 @@ def main():
     }
     if "f16" in results and "f32" in results:
         line["f16_over_f32_mlups"] = round(results["f16"]["mlups"] / results["f32"]["mlups"], 3)
+    if "s16" in results and "f32" in results:
+        line["s16_over_f32_mlups"] = round(results["s16"]["mlups"] / results["f32"]["mlups"], 3)
+    if not args.no_accuracy:
+        log("[bench] accuracy against the stored FP64 oracle results (1000 steps per codec)")
+        acc = accuracy_vs_oracle(torch, lbm, cfg, list(results))
+        if acc is not None:
+            line["accuracy_vs_oracle"] = acc
     if not args.no_inplace and n == 512:
         log("[bench] one-array (in-place) FP32")
         line["inplace_f32"] = run_inplace(torch, lbm, cfg, args.steps, args.reps)

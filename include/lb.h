@@ -22,8 +22,8 @@
  *    Weights: 1/3 (rest), 1/18 (axis), 1/36 (diagonal).
  *  - The stored state is the post-collision population array.  It is kept
  *    shifted by the lattice weights, g_i = f_i - w_i, in the storage codec
- *    chosen at creation (FP32, or FP16 / BF16 rounded to nearest even); all
- *    arithmetic is FP32.
+ *    chosen at creation (FP32, FP16 / BF16 rounded to nearest even, or the
+ *    scaled 16-bit fixed point LB_S16); all arithmetic is FP32.
  *  - "Device" pointers are HIP device memory owned by the caller; the library
  *    never frees them.  Calls that take device pointers are enqueued on the
  *    lattice's stream and return before the work completes.
@@ -56,6 +56,24 @@ typedef struct lb_lattice lb_lattice;
 #define LB_F32 0   /* FP32 storage of g = f - w, 4 bytes per population      */
 #define LB_F16S 1  /* FP16 storage of g = f - w, round-to-nearest-even        */
 #define LB_BF16S 2 /* BF16 storage of g = f - w, round-to-nearest-even        */
+/*
+ * LB_S16: scaled 16-bit fixed point of g = f - w (a custom 16-bit codec for
+ * the storage-precision question of Section 3.1.1; arithmetic stays FP32).
+ * Population i is stored as the int16 code q with g_i = q * 2^-e, with one
+ * exponent e per weight class (rest, axis, diagonal) for the whole lattice.
+ * lb_init_eq sizes each class from the initial state (|g_i| <= w_i 2^m with
+ * 2^m at least twice the class's largest |g_i| / w_i).  Encoding rounds to
+ * nearest even.  A step in which a code would leave [-32768, 32767] (or a
+ * density is not finite) flags itself with the classes concerned; the steps
+ * after it do nothing, and the next call that waits for the lattice
+ * (lb_sync, lb_sums, lb_macros, lb_get_f, ...) widens those classes' ranges
+ * by one bit, re-encodes the intact source array of the flagged step and
+ * redoes the remaining steps, as often as needed (LB_EUNSTABLE past the
+ * widest range).  Two-array storage only; not with force fields, the adjoint or the
+ * outlet flux.  Raw words (lb_get_f) are the int16 codes; lb_get_scales gives
+ * their exponents.
+ */
+#define LB_S16 3
 
 /*
  * Flag OR-ed into the storage argument of lb_create_ex: keep ONE population
@@ -88,7 +106,7 @@ typedef struct lb_lattice lb_lattice;
 lb_lattice *lb_create(int nx, int ny, int nz, double tau, const uint8_t *flags);
 
 /*
- * As lb_create, with a storage codec (LB_F32, LB_F16S, LB_BF16S, optionally
+ * As lb_create, with a storage codec (LB_F32, LB_F16S, LB_BF16S, LB_S16, optionally
  * OR-ed with LB_INPLACE) and a HIP stream (hipStream_t passed as void*) on
  * which all of the lattice's work is enqueued.  NULL is the default stream.  The stream is borrowed: the
  * lattice never destroys it, and it must outlive the lattice.
@@ -200,6 +218,16 @@ int lb_set_f(lb_lattice *lat, const void *buf, size_t bytes, int where);
 /* Wait until all work enqueued on the lattice's stream has finished. */
 int lb_sync(lb_lattice *lat);
 
+/*
+ * LB_S16 storage only: the 3 exponents of the stored codes, for the rest,
+ * axis and diagonal populations (g_i = q_i 2^-e), after settling pending
+ * steps.  lb_set_scales sets them without touching the stored words, for
+ * restoring a checkpoint taken with lb_get_f and lb_get_scales (each in
+ * [4, 60]).  Other codecs: LB_EINVAL.
+ */
+int lb_get_scales(lb_lattice *lat, int *exps);
+int lb_set_scales(lb_lattice *lat, const int *exps);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char *lb_last_error(void);
 
@@ -214,8 +242,9 @@ long long lb_steps_done(const lb_lattice *lat);
  * and population), 1 = sites per thread, 2 = 1 if the lattice has solid
  * sites, 3 = bytes per stored population, 4 = workgroups per step launch,
  * 5 = x-rows per storage block, 6 = number of fluid sites, 7 = bytes of one
- * population array, 8 = 1 for in-place (one-array) storage.  Returns -1 for
- * an unknown key or a bad handle.
+ * population array, 8 = 1 for in-place (one-array) storage, 9 = storage
+ * codec, 10 = range widenings of LB_S16 storage so far.  Returns -1 for an
+ * unknown key or a bad handle.
  */
 long long lb_query(const lb_lattice *lat, int key);
 

@@ -21,10 +21,10 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "liblbm355.so")
 
 LB_OK, LB_EINVAL, LB_ENOMEM, LB_EHIP, LB_EUNSTABLE, LB_ESTATE = 0, -1, -2, -3, -4, -5
-LB_F32, LB_F16S, LB_BF16S = 0, 1, 2
+LB_F32, LB_F16S, LB_BF16S, LB_S16 = 0, 1, 2, 3
 LB_HOST, LB_DEVICE = 0, 1
 LB_INPLACE = 0x100
-CODECS = {"f32": LB_F32, "f16": LB_F16S, "bf16": LB_BF16S}
+CODECS = {"f32": LB_F32, "f16": LB_F16S, "bf16": LB_BF16S, "s16": LB_S16}
 
 # Every function the C ABI exports, with its ctypes signature.
 _P = ctypes.c_void_p
@@ -42,6 +42,8 @@ _SIGNATURES = {
     "lb_get_f": (ctypes.c_int, [_P, _P, ctypes.c_size_t, ctypes.c_int]),
     "lb_set_f": (ctypes.c_int, [_P, _P, ctypes.c_size_t, ctypes.c_int]),
     "lb_sync": (ctypes.c_int, [_P]),
+    "lb_get_scales": (ctypes.c_int, [_P, _P]),
+    "lb_set_scales": (ctypes.c_int, [_P, _P]),
     "lb_last_error": (ctypes.c_char_p, []),
     "lb_steps_done": (ctypes.c_longlong, [_P]),
     "lb_query": (ctypes.c_longlong, [_P, ctypes.c_int]),
@@ -213,6 +215,19 @@ class Lattice:
     def _raw_dtype(self):
         return np.float32 if self.codec == "f32" else np.uint16
 
+    def get_scales(self) -> np.ndarray:
+        """Exponents of scaled 16-bit storage (codec "s16") for the rest, axis
+        and diagonal populations: g_i = code * 2^-e."""
+        out = np.zeros(3, dtype=np.int32)
+        _check(lib().lb_get_scales(self._h, out.ctypes.data_as(ctypes.c_void_p)), "lb_get_scales")
+        return out
+
+    def set_scales(self, exps):
+        e = np.ascontiguousarray(exps, dtype=np.int32)
+        if e.shape != (3,):
+            raise ValueError("3 exponents expected (rest, axis, diagonal)")
+        _check(lib().lb_set_scales(self._h, e.ctypes.data_as(ctypes.c_void_p)), "lb_set_scales")
+
     def get_f(self) -> np.ndarray:
         """Raw stored state on the host: (19, nz, ny, nx) float32 or uint16 words."""
         out = np.empty((19, self.nz, self.ny, self.nx), dtype=self._raw_dtype())
@@ -292,7 +307,7 @@ class Lattice:
     @property
     def info(self) -> dict:
         keys = ["variant", "sites_per_thread", "solids", "bytes_per_population", "grid", "block_rows", "n_fluid",
-                "array_bytes", "inplace"]
+                "array_bytes", "inplace", "codec", "rescales"]
         return {k: self.query(i) for i, k in enumerate(keys)}
 
     def time_steps(self, n: int) -> float:
@@ -594,12 +609,19 @@ class Batch:
         return ms.value
 
 
-def decode_state(raw: np.ndarray, codec: str) -> np.ndarray:
-    """Raw stored words -> float64 shifted populations g = f - w (host-side view)."""
+def decode_state(raw: np.ndarray, codec: str, scales=None) -> np.ndarray:
+    """Raw stored words -> float64 shifted populations g = f - w (host-side
+    view).  Scaled 16-bit codes ("s16") need the lattice's 3 exponents
+    (Lattice.get_scales(): rest, axis, diagonal)."""
     if codec == "f32":
         return raw.astype(np.float64)
     if codec == "f16":
         return raw.view(np.float16).astype(np.float64)
+    if codec == "s16":
+        if scales is None:
+            raise ValueError("s16 codes need their exponents")
+        e = np.asarray(scales, dtype=np.float64)[[0] + [1] * 6 + [2] * 12]
+        return raw.view(np.int16).astype(np.float64) * np.exp2(-e).reshape((19,) + (1,) * (raw.ndim - 1))
     return (raw.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
 
 

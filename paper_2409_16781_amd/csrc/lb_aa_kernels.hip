@@ -116,7 +116,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(aa_waves
                             if (!((dead >> e) & 1u)) st_elem<C>(F, g.own + OPP[i] * a.lay.seg + e, vget<C, NW>(d[i], e));
                 }
             }
-            add_lane_totals<C, NW>(d, acc);
+            add_lane_totals<C, NW>(d, acc, a.sc);
         }
     }
     store_block_totals(acc, a.partials + 4 * (size_t)blockIdx.x);
@@ -165,7 +165,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(push_wav
                 }
         }
         if (g.active) {
-            add_lane_totals<C, NW>(d, acc);
+            add_lane_totals<C, NW>(d, acc, a.sc);
             // bounce-back: where x + c_i is solid (bit opp(i)), f*_i(x) stays at x, in slot opp(i)
             if constexpr (kSolids) {
 #pragma unroll

@@ -452,7 +452,7 @@ lb_batch *lb_batch_create(int count, const int *dims, const double *taus, const 
         return nullptr;
     }
     if (storage != LB_F32 && storage != LB_F16S && storage != LB_BF16S) {
-        fail(LB_EINVAL, "unknown storage codec %d", storage);
+        fail(LB_EINVAL, "storage codec %d is not available in batches (LB_F32, LB_F16S, LB_BF16S)", storage);
         return nullptr;
     }
     for (int k = 0; k < count; ++k) {

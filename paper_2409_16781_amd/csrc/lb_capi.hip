@@ -102,6 +102,15 @@ struct lb_lattice {
     std::vector<void *> adj_ws;  // state-sized buffers of the adjoint sweep, kept for later calls
     double *jval;     // device double: the outlet flux objective
     int dev;          // HIP device the lattice lives on
+    // scaled 16-bit storage (LB_S16): exponents, their device-side constants,
+    // the two per-parity overflow flags and the last settled point (steps and
+    // array) from which flagged steps are redone
+    int s16e[3];      // exponents of the rest, axis and diagonal populations
+    Scale16 sc;
+    unsigned int *ovf;
+    long long base_steps;
+    int base_cur;
+    long long rescales;
 };
 
 namespace {
@@ -145,6 +154,9 @@ StepArgs step_args(const lb_lattice *h, int from, float *rho, float *u, int vari
     a.u_out = u;
     a.partials = h->partials;
     a.fx_field = h->ffield;
+    a.sc = h->sc;
+    a.ovf = h->ovf;
+    a.par = from;
     return a;
 }
 
@@ -166,6 +178,7 @@ MacroArgs macro_args(const lb_lattice *h, int cur, float *rho, float *u)
     a.fx_field = h->ffield;
     a.rho = rho;
     a.u = u;
+    a.sc = h->sc;
     return a;
 }
 
@@ -228,10 +241,12 @@ TotalsBufs scratch_bufs(const lb_lattice *h, unsigned char *base)
     return tb;
 }
 
-// Totals of the step whose workgroup partials are in buffer buf (0 or 1).
-TotalsArgs totals_args(const lb_lattice *h, int buf, const TotalsBufs &tb)
+// Totals of the step whose workgroup partials are in buffer buf (0 or 1) and
+// whose source array is buf[par] (its overflow flag, for scaled storage).
+TotalsArgs totals_args(const lb_lattice *h, int buf, const TotalsBufs &tb, int par)
 {
     TotalsArgs t{};
+    t.ovf = h->codec == kS16 ? h->ovf + par : nullptr;
     t.partials = tb.partials + (size_t)buf * 4 * h->grid;
     t.nparts = h->grid;
     t.gpartials = tb.gpartials;
@@ -242,6 +257,85 @@ TotalsArgs totals_args(const lb_lattice *h, int buf, const TotalsBufs &tb)
     return t;
 }
 
+// ---- scaled 16-bit storage (LB_S16)
+
+// Exponent of weight class c for the bound |g_i| <= w_i 2^m: the largest e
+// with 32767 2^-e >= w_i 2^m, i.e. floor(log2(32767 / w_i)) - m (w = 1/3,
+// 1/18, 1/36).
+int s16_class_exponent(int c, int m) { return (c == 0 ? 16 : (c == 1 ? 19 : 20)) - m; }
+
+void s16_set_class_exponents(lb_lattice *h, int m)
+{
+    for (int c = 0; c < 3; ++c) h->s16e[c] = s16_class_exponent(c, m);
+}
+
+void s16_update_scales(lb_lattice *h)
+{
+    for (int c = 0; c < 3; ++c) {
+        const float d = std::ldexp(1.0f, -h->s16e[c]);
+        h->sc.dm[c] = d;
+        h->sc.da[c] = -8421376.0f * d;  // -(2^23 + 2^15) 2^-e: exact
+        h->sc.em[c] = std::ldexp(1.0f, h->s16e[c]);
+    }
+    h->graphs.invalidate();  // the scales are launch arguments
+}
+
+constexpr int kS16MinExp = 4;   // widest range: |g| < 2^11
+constexpr int kS16MaxExp = 60;  // narrowest range: |g| < 2^-45
+
+int enqueue_steps(lb_lattice *h, int n, float *rho, float *u);
+
+// Wait for the lattice's work; if a scaled-storage step overflowed, widen
+// the range of each weight class whose codes left it by one bit
+// (re-encoding the intact source array of the first flagged step), and redo
+// the flagged and skipped steps; repeat until no step is flagged.  Other
+// codecs: no-op.
+int settle(lb_lattice *h)
+{
+    if (h->codec != kS16) return LB_OK;
+    for (;;) {
+        unsigned int flag[2] = {0u, 0u};
+        unsigned long long ctr = 0;
+        HIP_OR_FAIL(hipMemcpyAsync(flag, h->ovf, sizeof flag, hipMemcpyDeviceToHost, h->stream));
+        HIP_OR_FAIL(hipMemcpyAsync(&ctr, h->counter, sizeof ctr, hipMemcpyDeviceToHost, h->stream));
+        HIP_OR_FAIL(hipStreamSynchronize(h->stream));
+        if (!flag[0] && !flag[1]) {
+            h->base_steps = h->steps;
+            h->base_cur = h->cur;
+            return LB_OK;
+        }
+        // the device counter counts the steps whose totals were appended:
+        // exactly the steps before the first flagged one
+        const long long good = (long long)ctr;
+        const long long pending = h->steps - good;
+        if (good < h->base_steps || pending < 1)
+            return fail(LB_ESTATE, "scaled storage: inconsistent overflow record (%lld good of %lld steps)", good,
+                        h->steps);
+        // the overflowing step's class bits (the steps skipped after it add
+        // only their skip bit)
+        unsigned int classes = (flag[0] | flag[1]) & 7u;
+        if (!classes) classes = 7u;
+        Shift16 sh;
+        for (int c = 0; c < 3; ++c) {
+            sh.sh[c] = (classes >> c) & 1u;
+            if (h->s16e[c] - sh.sh[c] < kS16MinExp)
+                return fail(LB_EUNSTABLE, "scaled 16-bit storage: values beyond the widest range at step %lld "
+                                          "(unstable run)", good + 1);
+        }
+        const int src = h->base_cur ^ (int)((good - h->base_steps) & 1);
+        HIP_OR_FAIL(launch_s16_rescale(h->buf[src], h->lay, h->arr_elems, sh, h->stream));
+        for (int c = 0; c < 3; ++c) h->s16e[c] -= sh.sh[c];
+        s16_update_scales(h);
+        HIP_OR_FAIL(launch_zero_words(h->ovf, 2, h->stream));
+        h->cur = src;
+        h->steps = good;
+        h->base_steps = good;
+        h->base_cur = src;
+        h->rescales += 1;
+        if (int rc = enqueue_steps(h, (int)pending, nullptr, nullptr)) return rc;
+    }
+}
+
 // Enqueue one step from buf[from] on stream s.
 int enqueue_one(lb_lattice *h, int from, float *rho, float *u, hipStream_t s, const TotalsBufs &tb)
 {
@@ -250,12 +344,12 @@ int enqueue_one(lb_lattice *h, int from, float *rho, float *u, hipStream_t s, co
     a.partials = tb.partials;
     if (h->inplace) {
         HIP_OR_FAIL(launch_aa_step(h->codec, h->variant, h->solids, from == 0, a, h->grid, s));
-        HIP_OR_FAIL(launch_totals(totals_args(h, 0, tb), s));
+        HIP_OR_FAIL(launch_totals(totals_args(h, 0, tb, from), s));
         if (macros) HIP_OR_FAIL(launch_macros(h->codec, macro_args(h, from ^ 1, rho, u), s));
         return LB_OK;
     }
     HIP_OR_FAIL(launch_step(h->codec, h->variant, h->solids, macros, a, h->grid, s));
-    HIP_OR_FAIL(launch_totals(totals_args(h, 0, tb), s));
+    HIP_OR_FAIL(launch_totals(totals_args(h, 0, tb, from), s));
     if (macros && h->solids && h->variant == 0)
         HIP_OR_FAIL(launch_zero_solid_macros(h->flags, (int)h->n, rho, u, s));
     return LB_OK;
@@ -278,10 +372,10 @@ int enqueue_run(lb_lattice *h, int from, int count, hipStream_t s, const TotalsB
     for (int k = 0; k < count; ++k) {
         StepArgs a = step_args(h, from ^ (k & 1), nullptr, nullptr);
         a.partials = tb.partials + (size_t)(k & 1) * 4 * h->grid;
-        if (k > 0) a.prev = totals_args(h, (k - 1) & 1, tb);
+        if (k > 0) a.prev = totals_args(h, (k - 1) & 1, tb, from ^ ((k - 1) & 1));
         HIP_OR_FAIL(launch_step(h->codec, h->variant, h->solids, false, a, h->grid, s));
     }
-    HIP_OR_FAIL(launch_totals(totals_args(h, (count - 1) & 1, tb), s));
+    HIP_OR_FAIL(launch_totals(totals_args(h, (count - 1) & 1, tb, from ^ ((count - 1) & 1)), s));
     return LB_OK;
 }
 
@@ -362,7 +456,8 @@ void release(lb_lattice *h)
 {
     h->graphs.release();
     void *ptrs[] = {h->alloc[0], h->alloc[1], h->flags,   h->nbmask, h->rowdirty, h->rowcum,
-                    h->partials, h->gpartials, h->ticket, h->ring,  h->counter, h->ffield, h->jval};
+                    h->partials, h->gpartials, h->ticket, h->ring,  h->counter, h->ffield, h->jval,
+                    h->ovf};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (void *p : h->adj_ws) (void)hipFree(p);
@@ -379,8 +474,9 @@ int create_impl(lb_lattice **out, int nx, int ny, int nz, double tau, const uint
     if (!(tau > 0.5)) return fail(LB_EINVAL, "tau must be > 0.5 or +inf (got %g)", tau);
     const bool inplace = (storage & LB_INPLACE) != 0;
     storage &= ~LB_INPLACE;
-    if (storage != LB_F32 && storage != LB_F16S && storage != LB_BF16S)
+    if (storage != LB_F32 && storage != LB_F16S && storage != LB_BF16S && storage != LB_S16)
         return fail(LB_EINVAL, "unknown storage codec %d", storage);
+    if (inplace && storage == LB_S16) return fail(LB_EINVAL, "scaled 16-bit storage needs two arrays (no LB_INPLACE)");
     uint64_t nsolid = 0;
     if (flags) {
         for (uint64_t s = 0; s < n; ++s) {
@@ -411,7 +507,9 @@ int create_impl(lb_lattice **out, int nx, int ny, int nz, double tau, const uint
     // of 4, one site per thread when no vector width divides nx.
     // LB_KERNEL (0..3) overrides the choice for tuning.
     const long kernel = env_long("LB_KERNEL", -1);
-    int variant = storage == LB_F32 ? 1 : 2;
+    // scaled 16-bit storage: 4-byte vectors (two sites per lane) keep its
+    // decode and encode within four waves per SIMD without spills
+    int variant = storage == LB_F32 ? 1 : (storage == LB_S16 ? 3 : 2);
     if (kernel >= 0 && kernel <= 3) variant = (int)kernel;
     else if (kernel != -1) {
         delete h;
@@ -528,6 +626,13 @@ int create_impl(lb_lattice **out, int nx, int ny, int nz, double tau, const uint
     if ((e = hipMemsetAsync(h->ticket, 0, sizeof(unsigned int), h->stream)) != hipSuccess) return bail(LB_EHIP, "hipMemsetAsync", e);
     if ((e = hipMemsetAsync(h->counter, 0, sizeof(unsigned long long), h->stream)) != hipSuccess) return bail(LB_EHIP, "hipMemsetAsync", e);
     if ((e = hipMemsetAsync(h->ring, 0, (size_t)kRingCap * 4 * sizeof(double), h->stream)) != hipSuccess) return bail(LB_EHIP, "hipMemsetAsync", e);
+    if (storage == LB_S16) {
+        // two per-parity overflow flags and three words for the initial maxima
+        if ((e = hipMalloc(&h->ovf, 8 * sizeof(unsigned int))) != hipSuccess) return bail(LB_ENOMEM, "hipMalloc", e);
+        if ((e = hipMemsetAsync(h->ovf, 0, 8 * sizeof(unsigned int), h->stream)) != hipSuccess) return bail(LB_EHIP, "hipMemsetAsync", e);
+        s16_set_class_exponents(h, -4);  // |g_i| <= w_i / 16 until lb_init_eq sizes the ranges
+        s16_update_scales(h);
+    }
     if (h->solids) {
         if ((e = hipMalloc(&h->flags, n)) != hipSuccess) return bail(LB_ENOMEM, "hipMalloc(flags)", e);
         if ((e = hipMalloc(&h->nbmask, n * sizeof(uint32_t) + 64)) != hipSuccess) return bail(LB_ENOMEM, "hipMalloc(masks)", e);
@@ -597,10 +702,33 @@ int lb_init_eq(lb_lattice *h, const double *rho, const double *u)
     a.u = u;
     a.flags = h->flags;
     a.swap = h->inplace ? 1 : 0;
+    if (h->codec == kS16) {
+        // size the ranges from the initial state: |g_i| <= w_i 2^m with
+        // 2^m >= 2 max |g_i^eq| / w_i (one bit of headroom); later growth is
+        // caught by the overflow flags
+        HIP_OR_FAIL(launch_eq_absmax(a, h->ovf + 2, h->stream));
+        unsigned int bits[3] = {0u, 0u, 0u};
+        HIP_OR_FAIL(hipMemcpyAsync(bits, h->ovf + 2, sizeof bits, hipMemcpyDeviceToHost, h->stream));
+        HIP_OR_FAIL(hipStreamSynchronize(h->stream));
+        for (int c = 0; c < 3; ++c) {
+            float mx = 0.0f;
+            std::memcpy(&mx, &bits[c], sizeof mx);
+            if (!std::isfinite(mx)) return fail(LB_EINVAL, "initial fields are not finite");
+            // at rest (mx = 0) the class gets |g| <= w / 16
+            int m = mx > 0.0f ? (int)std::ceil(std::log2(2.0 * (double)mx)) : -4;
+            m = std::min(3, std::max(-30, m));
+            h->s16e[c] = s16_class_exponent(c, m);
+        }
+        s16_update_scales(h);
+        a.sc = h->sc;
+        HIP_OR_FAIL(launch_zero_words(h->ovf, 2, h->stream));
+    }
     HIP_OR_FAIL(launch_init(h->codec, a, h->stream));
     HIP_OR_FAIL(hipMemsetAsync(h->counter, 0, sizeof(unsigned long long), h->stream));
     h->cur = 0;
     h->steps = 0;
+    h->base_steps = 0;
+    h->base_cur = 0;
     return LB_OK;
 }
 
@@ -638,12 +766,21 @@ int lb_step_macros(lb_lattice *h, int n, float *rho, float *u)
     if (int rc = check(h)) return rc;
     if (n < 1) return fail(LB_EINVAL, "lb_step_macros needs n >= 1 (got %d)", n);
     if (!rho || !u) return fail(LB_EINVAL, "rho and u must be device pointers");
+    if (h->codec == kS16) {
+        // the fields of the settled state (a redone step must not leave its
+        // first attempt's fields behind)
+        if (int rc = enqueue_steps(h, n, nullptr, nullptr)) return rc;
+        if (int rc = settle(h)) return rc;
+        HIP_OR_FAIL(launch_macros(h->codec, macro_args(h, h->cur, rho, u), h->stream));
+        return LB_OK;
+    }
     return enqueue_steps(h, n, rho, u);
 }
 
 int lb_macros(lb_lattice *h, float *rho, float *u)
 {
     if (int rc = check(h)) return rc;
+    if (int rc = settle(h)) return rc;
     HIP_OR_FAIL(launch_macros(h->codec, macro_args(h, h->cur, rho, u), h->stream));
     return LB_OK;
 }
@@ -841,6 +978,7 @@ int lb_outlet_flux(lb_lattice *h, double *J)
     if (int rc = check(h)) return rc;
     if (!J) return fail(LB_EINVAL, "J must be a host pointer");
     if (h->inplace) return fail(LB_EINVAL, "the outlet flux needs two-array storage");
+    if (h->codec == kS16) return fail(LB_EINVAL, "the outlet flux needs FP32, FP16 or BF16 storage");
     return outlet_flux_value(h, J);
 }
 
@@ -851,6 +989,7 @@ int lb_sums(lb_lattice *h, double *out, int k)
     if (k < 0 || !out) return fail(LB_EINVAL, "bad output buffer or k");
     const long long avail = h->steps < kRingCap ? h->steps : kRingCap;
     if (k > avail) return fail(LB_EINVAL, "asked for %d step totals, %lld available", k, avail);
+    if (int rc = settle(h)) return rc;
     HIP_OR_FAIL(hipStreamSynchronize(h->stream));
     std::vector<double> ring((size_t)kRingCap * 4);
     HIP_OR_FAIL(hipMemcpy(ring.data(), h->ring, ring.size() * sizeof(double), hipMemcpyDeviceToHost));
@@ -870,6 +1009,7 @@ int lb_sums(lb_lattice *h, double *out, int k)
 static int copy_f(lb_lattice *h, void *host_or_dev, size_t bytes, int where, bool to_lattice)
 {
     if (int rc = check(h)) return rc;
+    if (int rc = settle(h)) return rc;
     const size_t want = (size_t)kQ * h->n * h->esize;
     if (bytes != want) return fail(LB_EINVAL, "buffer is %zu bytes, expected %zu", bytes, want);
     if (!host_or_dev) return fail(LB_EINVAL, "NULL buffer");
@@ -937,13 +1077,43 @@ int lb_get_f(lb_lattice *h, void *buf, size_t bytes, int where) { return copy_f(
 
 int lb_set_f(lb_lattice *h, const void *buf, size_t bytes, int where)
 {
-    return copy_f(h, const_cast<void *>(buf), bytes, where, true);
+    const int rc = copy_f(h, const_cast<void *>(buf), bytes, where, true);
+    if (rc == LB_OK) {
+        h->base_steps = h->steps;
+        h->base_cur = h->cur;
+    }
+    return rc;
 }
 
 int lb_sync(lb_lattice *h)
 {
     if (int rc = check(h)) return rc;
+    if (int rc = settle(h)) return rc;
     HIP_OR_FAIL(hipStreamSynchronize(h->stream));
+    return LB_OK;
+}
+
+int lb_get_scales(lb_lattice *h, int *exps)
+{
+    if (int rc = check(h)) return rc;
+    if (h->codec != kS16) return fail(LB_EINVAL, "scales exist for LB_S16 storage only");
+    if (!exps) return fail(LB_EINVAL, "NULL exponent array");
+    if (int rc = settle(h)) return rc;
+    for (int c = 0; c < 3; ++c) exps[c] = h->s16e[c];
+    return LB_OK;
+}
+
+int lb_set_scales(lb_lattice *h, const int *exps)
+{
+    if (int rc = check(h)) return rc;
+    if (h->codec != kS16) return fail(LB_EINVAL, "scales exist for LB_S16 storage only");
+    if (!exps) return fail(LB_EINVAL, "NULL exponent array");
+    for (int c = 0; c < 3; ++c)
+        if (exps[c] < kS16MinExp || exps[c] > kS16MaxExp)
+            return fail(LB_EINVAL, "exponent %d of weight class %d outside [%d, %d]", exps[c], c, kS16MinExp, kS16MaxExp);
+    if (int rc = settle(h)) return rc;
+    for (int c = 0; c < 3; ++c) h->s16e[c] = exps[c];
+    s16_update_scales(h);
     return LB_OK;
 }
 
@@ -966,6 +1136,8 @@ long long lb_query(const lb_lattice *h, int key)
         case 6: return (long long)h->n_fluid;
         case 7: return (long long)(h->arr_elems * h->esize);
         case 8: return h->inplace ? 1 : 0;
+        case 9: return h->codec;
+        case 10: return h->rescales;
         default: return -1;
     }
 }
@@ -986,6 +1158,7 @@ int lb_time_steps(lb_lattice *h, int n, double *ms)
     float t = 0.0f;
     if (rc == LB_OK && hipEventElapsedTime(&t, e0, e1) != hipSuccess) rc = fail(LB_EHIP, "hipEventElapsedTime");
     if (rc == LB_OK) *ms = t;
+    if (rc == LB_OK) rc = settle(h);  // scaled storage: redo flagged steps (outside the timed region)
     return rc;
 }
 
@@ -1004,7 +1177,7 @@ int lb_time_step_kernel(lb_lattice *h, int n, double *ms)
                                          : launch_step(h->codec, h->variant, h->solids, false, a, h->grid, h->stream);
         if (rc == LB_OK && le != hipSuccess) rc = fail(LB_EHIP, "step kernel launch");
         if (rc == LB_OK && hipEventRecord(ev[2 * k + 1], h->stream) != hipSuccess) rc = fail(LB_EHIP, "hipEventRecord");
-        if (rc == LB_OK && launch_totals(totals_args(h, 0, own_bufs(h)), h->stream) != hipSuccess) rc = fail(LB_EHIP, "totals launch");
+        if (rc == LB_OK && launch_totals(totals_args(h, 0, own_bufs(h), h->cur), h->stream) != hipSuccess) rc = fail(LB_EHIP, "totals launch");
         if (rc == LB_OK) {
             h->cur ^= 1;
             h->steps += 1;
@@ -1020,6 +1193,7 @@ int lb_time_step_kernel(lb_lattice *h, int n, double *ms)
     for (auto &e : ev)
         if (e) (void)hipEventDestroy(e);
     if (rc == LB_OK) *ms = total / n;
+    if (rc == LB_OK) rc = settle(h);
     return rc;
 }
 
@@ -1027,6 +1201,7 @@ int lb_copy_probe(lb_lattice *h, int reps, double *ms)
 {
     if (int rc = check(h)) return rc;
     if (reps < 1 || !ms) return fail(LB_EINVAL, "reps must be >= 1 and ms non-NULL");
+    if (int rc = settle(h)) return rc;  // the probe overwrites the other array
     const uint64_t bytes = ((uint64_t)h->arr_elems * h->esize) & ~(uint64_t)15;
     Events evs(2);
     HIP_OR_FAIL(evs.create());

@@ -251,6 +251,102 @@ struct Codec<kBF16> {
     }
 };
 
+// Scaled 16-bit fixed point (see Scale16): the stored word is the int16 q,
+// g_i = q 2^-e_i.  Decoding puts q + 2^15 into the low mantissa bits of the
+// float 2^23 (exact), then one FMA applies the scale; encoding is one FMA
+// that lands on the integer grid of [2^23, 2^24) (round to nearest even) and
+// keeps the low 16 bits, back in two's complement.  A value whose code falls
+// outside [-2^15, 2^15) shows as a float outside [2^23, 2^23 + 2^16); the
+// step kernels track the extremes and flag such a step.
+template <>
+struct Codec<kS16> {
+    static constexpr int kBytes = 2;
+    static constexpr float kBias = 8421376.0f;  // 2^23 + 2^15
+    static constexpr float kLo = 8388608.0f;     // 2^23: code -2^15
+    static constexpr float kHi = 8454143.0f;     // 2^23 + 2^16 - 1: code 2^15 - 1
+    // word (zero-extended) -> the float 2^23 + 2^15 + q
+    __device__ static float biased(uint32_t b) { return __builtin_bit_cast(float, ((b & 0xffffu) ^ 0x8000u) + 0x4B000000u); }
+    // float on the integer grid of [2^23, 2^24) -> word
+    __device__ static uint32_t word(float f) { return (__builtin_bit_cast(uint32_t, f) ^ 0x8000u) & 0xffffu; }
+};
+
+constexpr uint32_t kS16Skipped = 8u;  // flag bit of a step skipped after a flagged one
+
+// Stored bits of population i -> value (the scale matters to kS16 only).
+template <int C>
+__device__ __forceinline__ float dec_at(uint32_t b, const Scale16 &sc, int i)
+{
+    if constexpr (C == kS16)
+        return fmaf(Codec<kS16>::biased(b), sc.dm[weight_class(i)], sc.da[weight_class(i)]);
+    else
+        return Codec<C>::dec(b);
+}
+
+// Extremes of the biased kS16 codes per weight class, tracked while encoding
+// and tested once per lane.
+struct Range16 {
+    float lo[3], hi[3];
+    __device__ Range16()
+    {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) lo[c] = hi[c] = 8421376.0f;  // the code of zero
+    }
+    // bit c: a code of weight class c left [-2^15, 2^15)
+    __device__ uint32_t out_bits() const
+    {
+        uint32_t b = 0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) b |= (lo[c] >= 8388608.0f && hi[c] <= 8454143.0f) ? 0u : (1u << c);
+        return b;
+    }
+};
+
+// Value of population i -> stored bits (kS16 also widens r to the code).
+template <int C>
+__device__ __forceinline__ uint32_t enc_at(float v, const Scale16 &sc, int i, Range16 &r)
+{
+    if constexpr (C == kS16) {
+        const int c = weight_class(i);
+        const float f = fmaf(v, sc.em[c], Codec<kS16>::kBias);
+        r.lo[c] = fminf(r.lo[c], f);
+        r.hi[c] = fmaxf(r.hi[c], f);
+        return Codec<kS16>::word(f);
+    } else {
+        return Codec<C>::enc(v);
+    }
+}
+
+// Two values of population i packed in one dword (16-bit codecs).
+template <int C>
+__device__ __forceinline__ void dec2_at(uint32_t w, const Scale16 &sc, int i, float &a, float &b)
+{
+    if constexpr (C == kS16) {
+        a = dec_at<C>(w & 0xffffu, sc, i);
+        b = dec_at<C>(w >> 16, sc, i);
+    } else {
+        Codec<C>::dec2(w, a, b);
+    }
+}
+
+template <int C>
+__device__ __forceinline__ uint32_t enc2_at(float a, float b, const Scale16 &sc, int i, Range16 &r)
+{
+    if constexpr (C == kS16)
+        return enc_at<C>(a, sc, i, r) | (enc_at<C>(b, sc, i, r) << 16);
+    else
+        return Codec<C>::enc2(a, b);
+}
+
+// Exact FP64 value of stored bits b of population i.
+template <int C>
+__device__ __forceinline__ double dec64_at(uint32_t b, const Scale16 &sc, int i)
+{
+    if constexpr (C == kS16)
+        return (double)(int16_t)(uint16_t)b * (double)sc.dm[weight_class(i)];
+    else
+        return (double)Codec<C>::dec(b);
+}
+
 // Element e of a lane vector, as raw bits.
 template <int C, int NW>
 __device__ __forceinline__ uint32_t vget(const Lane<NW> &d, int e)
@@ -400,16 +496,25 @@ __device__ __forceinline__ void moments_of_totals(const T (&t)[kQ], T &m, T &px,
 // elements hold zero and add nothing).  The stored values are exact in
 // double, so a lane's totals carry only FP64 rounding (~1e-16 relative).
 template <int C, int NW>
-__device__ __forceinline__ void add_lane_totals(const Lane<NW> (&d)[kQ], double (&acc)[4])
+__device__ __forceinline__ void add_lane_totals(const Lane<NW> (&d)[kQ], double (&acc)[4], const Scale16 &sc)
 {
     using K = Codec<C>;
     constexpr int V = NW * 4 / K::kBytes;
     double m = 0.0, px = 0.0, py = 0.0, pz = 0.0;
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
-        double t = (double)K::dec(vget<C, NW>(d[i], 0));
+        double t;
+        if constexpr (C == kS16) {
+            // integer codes sum exactly; one exact scaling by 2^-e_i
+            int qs = (int16_t)(uint16_t)vget<C, NW>(d[i], 0);
 #pragma unroll
-        for (int e = 1; e < V; ++e) t += (double)K::dec(vget<C, NW>(d[i], e));
+            for (int e = 1; e < V; ++e) qs += (int16_t)(uint16_t)vget<C, NW>(d[i], e);
+            t = (double)qs * (double)sc.dm[weight_class(i)];
+        } else {
+            t = (double)K::dec(vget<C, NW>(d[i], 0));
+#pragma unroll
+            for (int e = 1; e < V; ++e) t += (double)K::dec(vget<C, NW>(d[i], e));
+        }
         m += t;
         if (CX[i] > 0) px += t;
         if (CX[i] < 0) px -= t;
@@ -855,6 +960,19 @@ __device__ __forceinline__ Coll coll_at(const Coll &p, float fx)
     return q;
 }
 
+// kS16: a lane whose codes left their class's range, or one of whose sites
+// has a density that is not finite (the fixed point would hide a NaN), flags
+// the step with the classes to widen (all three for a non-finite density);
+// the step is redone from its intact source array with wider ranges.
+template <int V>
+__device__ __forceinline__ void s16_flag(const StepArgs &a, const Range16 &r, const float (&rho)[V])
+{
+    uint32_t bits = r.out_bits();
+#pragma unroll
+    for (int e = 0; e < V; ++e) bits |= fabsf(rho[e]) < 1e30f ? 0u : 7u;
+    if (bits) __hip_atomic_fetch_or(&a.ovf[a.par], bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // One tile (kBlock lanes, V sites each) of lattice a: gather with periodic
 // wrap and bounce-back, collide, store into dst, and add the FP64 totals of
 // the tile's fluid sites to acc.  kPadded: rows are stored with pitch > nx
@@ -876,6 +994,7 @@ __device__ __forceinline__ void tile_update(const StepArgs &a, const char *src, 
 
     // collide site by site (16-bit codecs: two sites per dword at a time)
     float mr[V], mu[V], mv[V], mw[V];
+    Range16 rng;  // kS16: extremes of the biased codes
     if constexpr (K::kBytes == 4) {
         float fxs[V];
         if constexpr (kFField) {
@@ -906,11 +1025,11 @@ __device__ __forceinline__ void tile_update(const StepArgs &a, const char *src, 
             for (int h = 0; h < 2; ++h) {
                 float gg[kQ];
 #pragma unroll
-                for (int i = 0; i < kQ; ++i) gg[i] = K::dec(h ? d[i].w[j] >> 16 : d[i].w[j] & 0xffffu);
+                for (int i = 0; i < kQ; ++i) gg[i] = dec_at<C>(h ? d[i].w[j] >> 16 : d[i].w[j] & 0xffffu, a.sc, i);
                 collide(gg, cp, mr[2 * j + h], mu[2 * j + h], mv[2 * j + h], mw[2 * j + h]);
 #pragma unroll
                 for (int i = 0; i < kQ; ++i) {
-                    const uint32_t b = K::enc(gg[i]);
+                    const uint32_t b = enc_at<C>(gg[i], a.sc, i, rng);
                     d[i].w[j] = h ? ((d[i].w[j] & 0xffffu) | (b << 16)) : ((d[i].w[j] & 0xffff0000u) | b);
                 }
                 // the packed words as they now stand: the next site decodes
@@ -927,11 +1046,11 @@ __device__ __forceinline__ void tile_update(const StepArgs &a, const char *src, 
         for (int j = 0; j < NW; ++j) {
             float g0[kQ], g1[kQ];
 #pragma unroll
-            for (int i = 0; i < kQ; ++i) K::dec2(d[i].w[j], g0[i], g1[i]);
+            for (int i = 0; i < kQ; ++i) dec2_at<C>(d[i].w[j], a.sc, i, g0[i], g1[i]);
             collide(g0, cp, mr[2 * j], mu[2 * j], mv[2 * j], mw[2 * j]);
             collide(g1, cp, mr[2 * j + 1], mu[2 * j + 1], mv[2 * j + 1], mw[2 * j + 1]);
 #pragma unroll
-            for (int i = 0; i < kQ; ++i) d[i].w[j] = K::enc2(g0[i], g1[i]);
+            for (int i = 0; i < kQ; ++i) d[i].w[j] = enc2_at<C>(g0[i], g1[i], a.sc, i, rng);
         }
     }
 
@@ -965,8 +1084,25 @@ __device__ __forceinline__ void tile_update(const StepArgs &a, const char *src, 
             store_floats<V>(a.u_out + 2 * n + g.s0, mw);
         }
         // totals of the values as stored (after rounding), fluid sites only
-        add_lane_totals<C, NW>(d, acc);
+        add_lane_totals<C, NW>(d, acc, a.sc);
     }
+    if constexpr (C == kS16) s16_flag(a, rng, mr);
+}
+
+// kS16 steps start here: a step whose predecessor was flagged (overflowed,
+// or skipped itself) marks its own parity as skipped and does nothing, so
+// the source array of the first flagged step stays intact.
+template <int C>
+__device__ __forceinline__ bool s16_skip(const StepArgs &a)
+{
+    if constexpr (C == kS16) {
+        if (__hip_atomic_load(&a.ovf[a.par ^ 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+            if (threadIdx.x == 0)
+                __hip_atomic_fetch_or(&a.ovf[a.par], kS16Skipped, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return true;
+        }
+    }
+    return false;
 }
 
 inline int grid_for(uint64_t n, int cap = 65536)

@@ -11,7 +11,21 @@ constexpr int kQ = 19;
 constexpr int kBlock = 256;        // threads per workgroup of every lattice kernel
 constexpr int kRingCap = 4096;     // per-step conservation totals kept on the device
 
-enum Codec : int { kF32 = 0, kF16 = 1, kBF16 = 2 };
+enum Codec : int { kF32 = 0, kF16 = 1, kBF16 = 2, kS16 = 3 };
+
+// Scales of the scaled 16-bit fixed-point codec (kS16): population i is
+// stored as the int16 q with g_i = q 2^-e_c, one exponent per weight class c
+// (rest, axis, diagonal) for the whole lattice.  dm = 2^-e_c, da = -(2^23 +
+// 2^15) 2^-e_c (decode: the float with bits 0x4B000000 + (q + 2^15), times
+// dm, plus da: exact); em = 2^e_c (encode: g em + 2^23 + 2^15 rounds to
+// nearest even at the integer).
+struct Scale16 {
+    float dm[3], da[3], em[3];
+};
+
+struct Shift16 {
+    int sh[3];  // per weight class: codes divided by 2^sh (widening the range)
+};
 
 // Division by a runtime constant d >= 1 for numerators n < 2^31:
 // q = (umulhi(n, m) + n) >> l with l = ceil(log2 d), m = floor(2^32 (2^l - d) / d) + 1
@@ -74,6 +88,8 @@ struct TotalsArgs {
     double *ring;             // kRingCap x 4 doubles
     unsigned long long *step_counter;
     double n_fluid;           // number of fluid sites (exact in a double)
+    const unsigned int *ovf;  // kS16: overflow flag of the step whose totals these are (set: no
+                              // totals appended), or nullptr
 };
 
 // Everything one step launch needs.  Pointers are device pointers.
@@ -97,6 +113,10 @@ struct StepArgs {
     const float *fx_field;    // optional per-site x-force added to coll.fx (N floats, site order) or nullptr
     TotalsArgs prev;          // prev.partials != nullptr: workgroup 0 also appends the totals of the
                               // step whose partials these are (written by the previous launch) to the ring
+    Scale16 sc;               // kS16 only
+    unsigned int *ovf;        // kS16 only: two flag words; this step ORs into ovf[par] bit c when a code
+    int par;                  // of weight class c leaves its range, and skips (ORing bit 3 into ovf[par])
+                              // when ovf[par ^ 1] is set
 };
 
 // One lattice of a batch.  The step arguments of domain d are s, with the
@@ -183,6 +203,7 @@ struct InitArgs {
     const double *u;          // 3N or nullptr
     const uint8_t *flags;     // device flags or nullptr
     int swap;                 // 1: population i goes to slot opp(i) (in-place storage, even phase)
+    Scale16 sc;               // kS16 only
 };
 
 struct MacroArgs {
@@ -196,6 +217,7 @@ struct MacroArgs {
     const uint8_t *flags;
     float *rho;
     float *u;
+    Scale16 sc;               // kS16 only
 };
 
 // Launchers (lb_kernels.hip).  variant: 0 = one site per thread; 1 / 2 / 3 = vector
@@ -213,6 +235,11 @@ hipError_t launch_masks(const uint8_t *flags, int nx, int ny, int nz, int pitch,
 hipError_t launch_zero_solid_macros(const uint8_t *flags, int n, float *rho, float *u, hipStream_t s);
 hipError_t launch_copy(const void *src, void *dst, uint64_t bytes, hipStream_t s);
 hipError_t launch_zero_words(unsigned int *p, int n, hipStream_t s);  // n words set to 0 by a kernel
+// kS16: max over fluid sites of |g_i^eq| / w_i per weight class of the
+// equilibrium init_eq writes (float bits into out[0..2]), and the in-place
+// widening of an array's scales
+hipError_t launch_eq_absmax(const InitArgs &a, unsigned int *out, hipStream_t s);
+hipError_t launch_s16_rescale(void *state, const Layout &lay, uint64_t elems, const Shift16 &sh, hipStream_t s);
 int step_occupancy(int codec, int variant, bool solids, bool macros);  // workgroups per CU
 
 // Host helpers of the runtime files.  fail() records the message that

@@ -41,6 +41,8 @@ __global__ __launch_bounds__(kBlock) void zero_words(unsigned int *p, int n)
 __global__ __launch_bounds__(kBlock) void reduce_totals(TotalsArgs a)
 {
     __shared__ int is_last;
+    // kS16: a flagged step has no totals (it is redone)
+    if (a.ovf != nullptr && __hip_atomic_load(a.ovf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) return;
     const int first = blockIdx.x * kRedChunk;
     const int count = min(kRedChunk, a.nparts - first);
     double gs[4];
@@ -79,6 +81,7 @@ template <int C, int NW, bool kSolids, bool kMacros, bool kFField = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(vec_waves<C, NW>()))) void step_vec(StepArgs a)
 {
     __shared__ EdgeLds lds;
+    if (s16_skip<C>(a)) return;
     const char *src = reinterpret_cast<const char *>(a.src);
     char *dst = reinterpret_cast<char *>(a.dst);
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -96,13 +99,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(vec_wave
 template <int C, bool kSolids, bool kMacros>
 __global__ __launch_bounds__(kBlock) void step_site(StepArgs a)
 {
-    using K = Codec<C>;
+    if (s16_skip<C>(a)) return;
     const Coll &cp = a.coll;
     const uint32_t nx = (uint32_t)a.nx, ny = (uint32_t)a.ny, nz = (uint32_t)a.nz;
     const char *src = reinterpret_cast<const char *>(a.src);
     char *dst = reinterpret_cast<char *>(a.dst);
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     const int ntiles = (a.nslots + kBlock - 1) / kBlock;
+    Range16 rng;  // kS16: extremes of the biased codes
+    float rho_bad = 0.0f;
 
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int slot = tile * kBlock + (int)threadIdx.x;
@@ -132,16 +137,17 @@ __global__ __launch_bounds__(kBlock) void step_site(StepArgs a)
                 b = ld_elem<C>(src, own + OPP[i] * a.lay.seg);
             else
                 b = ld_elem<C>(src, a.lay.row_base(zs * ny + ys) + i * a.lay.seg + xs);
-            g[i] = K::dec(b);
+            g[i] = dec_at<C>(b, a.sc, i);
         }
         float rho, ux, uy, uz;
         collide(g, cp, rho, ux, uy, uz);
+        if (!(fabsf(rho) < 1e30f)) rho_bad = rho;
         double tot[kQ];
 #pragma unroll
         for (int i = 0; i < kQ; ++i) {
-            const uint32_t b = K::enc(g[i]);
+            const uint32_t b = enc_at<C>(g[i], a.sc, i, rng);
             st_elem<C>(dst, own + i * a.lay.seg, b);
-            tot[i] = (double)K::dec(b);
+            tot[i] = dec64_at<C>(b, a.sc, i);
         }
         if constexpr (kMacros) {
             const size_t n = (size_t)nx * ny * nz;
@@ -156,6 +162,10 @@ __global__ __launch_bounds__(kBlock) void step_site(StepArgs a)
         acc[1] += px;
         acc[2] += py;
         acc[3] += pz;
+    }
+    if constexpr (C == kS16) {
+        const float rb[1] = {rho_bad};
+        s16_flag<1>(a, rng, rb);
     }
     store_block_totals(acc, a.partials + 4 * (size_t)blockIdx.x);
 }
@@ -196,8 +206,57 @@ __global__ __launch_bounds__(kBlock) void init_eq(InitArgs a)
         for (int i = 0; i < kQ; ++i) {
             const double cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
             const double geq = w[weight_class(i)] * (drho + rho * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
-            st_elem<C>(dst, own + (a.swap ? OPP[i] : i) * a.lay.seg, solid ? 0u : K::enc64(geq));
+            uint32_t b;
+            if constexpr (C == kS16) {
+                // nearest code (ties to even), saturated (the host's scales leave headroom)
+                const double q = fmin(fmax(rint(geq * (double)a.sc.em[weight_class(i)]), -32768.0), 32767.0);
+                b = (uint32_t)(uint16_t)(int16_t)q;
+            } else {
+                b = K::enc64(geq);
+            }
+            st_elem<C>(dst, own + (a.swap ? OPP[i] : i) * a.lay.seg, solid ? 0u : b);
         }
+    }
+}
+
+// Largest |g_i^eq| / w_i per weight class (rest, axis, diagonal) over the
+// fluid sites of the equilibrium that init_eq writes (as float bits into
+// out[0..2]; non-negative floats order like their bits).  The scaled 16-bit
+// codec sizes its exponents from them.
+__global__ __launch_bounds__(kBlock) void eq_absmax(InitArgs a, unsigned int *out)
+{
+    float m[3] = {0.0f, 0.0f, 0.0f};  // per weight class
+    for (int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x; s < a.n; s += (int64_t)gridDim.x * kBlock) {
+        if (a.flags && a.flags[s]) continue;
+        const double rho = a.rho ? a.rho[s] : 1.0;
+        const double ux = a.u ? a.u[s] : 0.0;
+        const double uy = a.u ? a.u[(size_t)a.n + s] : 0.0;
+        const double uz = a.u ? a.u[2 * (size_t)a.n + s] : 0.0;
+        const double uu = ux * ux + uy * uy + uz * uz;
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) {
+            const double cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
+            const double r = (rho - 1.0) + rho * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);  // g_i^eq / w_i
+            m[weight_class(i)] = fmaxf(m[weight_class(i)], (float)fabs(r));
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        for (int off = 32; off >= 1; off >>= 1) m[c] = fmaxf(m[c], __shfl_xor(m[c], off, 64));
+        if ((threadIdx.x & 63) == 0) atomicMax(out + c, __builtin_bit_cast(unsigned int, m[c]));
+    }
+}
+
+// Widen the scales of a kS16 array in place: the code of population i is
+// divided by 2^shift (of its weight class) and rounded to nearest even (exact
+// in float: |q| < 2^15).
+__global__ __launch_bounds__(kBlock) void s16_rescale(uint16_t *state, Layout lay, uint64_t elems, Shift16 sh)
+{
+    for (uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x; k < elems; k += (uint64_t)gridDim.x * kBlock) {
+        const int i = (int)((k % lay.blk) / lay.seg);
+        const int c = i == 0 ? 0 : (i < 7 ? 1 : 2);
+        const float q = (float)(int16_t)state[k];
+        state[k] = (uint16_t)(int16_t)(int)rintf(q * __builtin_ldexpf(1.0f, -sh.sh[c]));
     }
 }
 
@@ -226,7 +285,6 @@ __device__ __forceinline__ uint32_t aa_fetch(const char *F, const Layout &lay, i
 template <int C>
 __global__ __launch_bounds__(kBlock) void macros_kernel(MacroArgs a)
 {
-    using K = Codec<C>;
     const char *src = reinterpret_cast<const char *>(a.src);
     for (int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x; s < a.n; s += (int64_t)gridDim.x * kBlock) {
         float r = 0.0f, ux = 0.0f, uy = 0.0f, uz = 0.0f;
@@ -237,8 +295,9 @@ __global__ __launch_bounds__(kBlock) void macros_kernel(MacroArgs a)
             float g[kQ];
 #pragma unroll
             for (int i = 0; i < kQ; ++i)
-                g[i] = K::dec(a.aa_phase ? aa_fetch<C>(src, a.lay, a.ny, a.nz, a.flags, a.aa_phase, i, x, row)
-                                         : ld_elem<C>(src, own + i * a.lay.seg));
+                g[i] = dec_at<C>(a.aa_phase ? aa_fetch<C>(src, a.lay, a.ny, a.nz, a.flags, a.aa_phase, i, x, row)
+                                            : ld_elem<C>(src, own + i * a.lay.seg),
+                                 a.sc, i);
             float m, px, py, pz;
             moments_of_totals(g, m, px, py, pz);
             r = 1.0f + m;
@@ -419,6 +478,7 @@ void *pick_step(int codec, int variant, bool solids, bool macros, bool ffield)
     switch (codec) {
         case kF32: LB_PICK(kF32)
         case kF16: LB_PICK(kF16)
+        case kS16: LB_PICK(kS16)
         default: LB_PICK(kBF16)
     }
 #undef LB_PICK
@@ -517,6 +577,7 @@ hipError_t launch_init(int codec, const InitArgs &a, hipStream_t s)
     switch (codec) {
         case kF32: init_eq<kF32><<<g, kBlock, 0, s>>>(a); break;
         case kF16: init_eq<kF16><<<g, kBlock, 0, s>>>(a); break;
+        case kS16: init_eq<kS16><<<g, kBlock, 0, s>>>(a); break;
         default: init_eq<kBF16><<<g, kBlock, 0, s>>>(a); break;
     }
     return hipGetLastError();
@@ -528,6 +589,7 @@ hipError_t launch_macros(int codec, const MacroArgs &a, hipStream_t s)
     switch (codec) {
         case kF32: macros_kernel<kF32><<<g, kBlock, 0, s>>>(a); break;
         case kF16: macros_kernel<kF16><<<g, kBlock, 0, s>>>(a); break;
+        case kS16: macros_kernel<kS16><<<g, kBlock, 0, s>>>(a); break;
         default: macros_kernel<kBF16><<<g, kBlock, 0, s>>>(a); break;
     }
     return hipGetLastError();
@@ -545,6 +607,19 @@ hipError_t launch_masks(const uint8_t *flags, int nx, int ny, int nz, int pitch,
 hipError_t launch_zero_solid_macros(const uint8_t *flags, int n, float *rho, float *u, hipStream_t s)
 {
     zero_solid_macros<<<grid_for((uint64_t)n), kBlock, 0, s>>>(flags, n, rho, u);
+    return hipGetLastError();
+}
+
+hipError_t launch_eq_absmax(const InitArgs &a, unsigned int *out, hipStream_t s)
+{
+    zero_words<<<1, kBlock, 0, s>>>(out, 3);
+    eq_absmax<<<grid_for((uint64_t)a.n, 4096), kBlock, 0, s>>>(a, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_s16_rescale(void *state, const Layout &lay, uint64_t elems, const Shift16 &sh, hipStream_t s)
+{
+    s16_rescale<<<grid_for(elems), kBlock, 0, s>>>(static_cast<uint16_t *>(state), lay, elems, sh);
     return hipGetLastError();
 }
 

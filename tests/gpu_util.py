@@ -113,10 +113,14 @@ C19 = np.array([(0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 
                 (-1, 0, -1), (0, 1, 1), (0, 1, -1), (0, -1, 1), (0, -1, -1)], dtype=np.float64)
 
 
-def decode_raw(raw, codec):
-    """Stored values g = f - w of a raw state (float32 or 16-bit words) as float64."""
+def decode_raw(raw, codec, exps=None):
+    """Stored values g = f - w of a raw state (float32 or 16-bit words) as
+    float64; scaled 16-bit codes ("s16") need their 3 exponents (rest, axis,
+    diagonal)."""
     if codec == "f32":
         return raw.astype(np.float64)
+    if codec == "s16":
+        return lbm.decode_state(raw, codec, exps)
     if codec == "f16":
         return raw.view(np.float16).astype(np.float64)
     if codec == "bf16":

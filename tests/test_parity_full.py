@@ -33,7 +33,7 @@ from gpu_util import bf16_bound, require_gpu, say
 pytestmark = pytest.mark.gpu
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-TOL = {"f32": 1e-5, "f16": 2e-3, "bf16": 2e-3}
+TOL = {"f32": 1e-5, "f16": 2e-3, "bf16": 2e-3, "s16": 2e-3}
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -114,6 +114,80 @@ def test_tgv512_noise_sampled_sites(tgv512_noise, codec):
     assert err <= TOL[codec]
     lat.close()
     torch.cuda.empty_cache()
+
+
+# ------------------------ 512^3 TGV + noise, 1000 steps, stored oracle -----
+# tests/golden/tgv512_noise_golden.{json,npz}: the FP64 oracle's u and rho at
+# 16384 seeded sites and whole-field statistics after 200 and 1000 steps of
+# this exact workload, written by make_tgv512_noise_golden.py from the oracle
+# alone.
+
+NOISE_GOLDEN = os.path.join(HERE, "golden", "tgv512_noise_golden")
+
+
+@pytest.fixture(scope="module")
+def noise_golden():
+    with open(NOISE_GOLDEN + ".json") as f:
+        meta = json.load(f)
+    with np.load(NOISE_GOLDEN + ".npz") as z:
+        arr = {k: z[k] for k in z.files}
+    return meta, arr
+
+
+def field_stats_gpu(torch, rho, u):
+    """The generator's whole-field statistics, evaluated on the GPU result in FP64."""
+    n = rho.shape[-1]
+    k = 2.0 * math.pi / n
+    x = torch.arange(n, dtype=torch.float64, device=rho.device)
+    mx = torch.outer(torch.cos(k * x), torch.sin(k * x))    # (y, x): sin kx cos ky
+    my = -torch.outer(torch.sin(k * x), torch.cos(k * x))   # -cos kx sin ky
+    ux, uy = u[0].double(), u[1].double()
+    proj = float((ux * mx).sum() + (uy * my).sum())
+    norm = float(rho.shape[0] * ((mx * mx).sum() + (my * my).sum()))
+    return dict(mode_amplitude=proj / norm,
+                sum_u2=[float((u[a].double() ** 2).sum()) for a in range(3)])
+
+
+@pytest.mark.skipif(not os.path.exists(NOISE_GOLDEN + ".npz"), reason="stored 512^3 oracle results missing")
+@pytest.mark.parametrize("codec", ["f32", "f16", "s16", "bf16"])
+def test_tgv512_noise_1000_steps_vs_stored_oracle(tgv512_noise, noise_golden, codec):
+    """The timed workload itself, at its stated 1000 steps: u at 16384 seeded
+    sites against the FP64 oracle (rel-L2 <= 1e-5 FP32, <= 2e-3 16-bit), the
+    amplitude of the Taylor-Green mode and the energy per component over the
+    whole field, and the mass total."""
+    torch = require_gpu()
+    meta, arr = noise_golden
+    cfg = tgv512_noise
+    n = 512
+    say(f"[gpu] tgv512 + noise {codec}: 1000 steps against the stored oracle results")
+    lat = lbm.Lattice(n, n, n, cfg["tau"], codec=codec)
+    lat.init_eq(torch.from_numpy(cfg["rho"]).cuda(), torch.from_numpy(cfg["u"]).cuda())
+    torch.cuda.empty_cache()
+    idx = torch.from_numpy(arr["sites_zyx"]).cuda()
+    done, err = 0, None
+    for k in (200, 1000):
+        lat.step(k - done)
+        done = k
+        r_g, u_g = lat.macros()
+        ug = u_g[:, idx[:, 0], idx[:, 1], idx[:, 2]].T.double().cpu().numpy()
+        err = rel_l2(ug, arr[f"u_{k}"])
+        st = field_stats_gpu(torch, r_g, u_g)
+        ref = meta["checkpoints"][str(k)]
+        mode_err = abs(st["mode_amplitude"] - ref["mode_amplitude"]) / abs(ref["mode_amplitude"])
+        e2_err = max(abs(st["sum_u2"][a] - ref["sum_u2"][a]) / ref["sum_u2"][a] for a in (0, 1))
+        mass = lat.sums(1)[0, 0]
+        mass_err = abs(mass - ref["sums"][0]) / ref["sums"][0]
+        say(f"  {k} steps: rel-L2(u) at {len(idx)} sites = {err:.3e}; mode amplitude {mode_err:.2e}, "
+            f"energy {e2_err:.2e}, mass {mass_err:.2e} (relative differences)")
+        del r_g, u_g
+        if codec != "bf16":
+            assert err <= TOL[codec]
+            assert mode_err <= TOL[codec] and e2_err <= 2 * TOL[codec]
+        assert mass_err <= 1e-8
+    lat.close()
+    torch.cuda.empty_cache()
+    if codec == "bf16":
+        bf16_bound(err)
 
 
 # --------------------------------------------- channel, 5000 steps ---------
