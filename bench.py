@@ -214,6 +214,7 @@ def run_adjoint(torch, lbm, reps):
     u = torch.from_numpy(cfg["u"]).cuda()
     lat.set_force_field(torch.zeros((n, n, n), dtype=torch.float32, device="cuda"))
     lat.init_eq(rho, u)
+    shape = lat.tune(10)  # forward (and recompute) launch shape for this lattice
     lat.grad_outlet_flux_x(20, 10)  # warm-up
     times = []
     for _ in range(reps):
@@ -230,6 +231,7 @@ def run_adjoint(torch, lbm, reps):
                          "mass flux w.r.t. the per-site x-force, 500 steps, copies every 50, FP32",
                 sites=n ** 3, fluid_sites=fl, steps=cfg["steps"], every=cfg["every"],
                 ms_per_gradient=round(dt * 1e3, 3),
+                forward_shape={k: shape[k] for k in ("variant", "sites_per_thread", "tile_order", "grid")},
                 site_steps_per_s=round(3 * cfg["steps"] * n ** 3 / dt / 1e6, 1),
                 note="forward + recompute + adjoint = 3 x steps site updates; the sweep's buffers are kept by the lattice "
                      "from the warm-up call on",
@@ -282,7 +284,8 @@ def run_small(torch, lbm, reps, steps=0):
             rho = torch.from_numpy(cfg["rho"]).cuda()
             u = torch.from_numpy(cfg["u"]).cuda()
             lat.init_eq(rho, u)
-            lat.step(64)  # warm-up: builds the step graphs
+            shape = lat.tune(10)  # launch shape for this lattice (state unchanged)
+            lat.step(64)  # warm-up
             times = []
             for _ in range(reps):
                 lat.init_eq(rho, u)
@@ -292,11 +295,14 @@ def run_small(torch, lbm, reps, steps=0):
             kernel_ms = lat.time_step_kernel(50)
             sums = lat.sums(1)
             lat.close()
+            nf = entry.get("fluid_sites", n)  # algorithmic bytes: fluid sites only
+            kgbs = bytes_per_site(codec) * nf / (kernel_ms * 1e-3) / 1e9
             entry[codec] = dict(mlups=round(n * cfg["steps"] / (ms * 1e-3) / 1e6, 1),
                                 ms_per_step=round(ms / cfg["steps"], 5),
-                                gbs_algorithmic=round(bytes_per_site(codec) * n * cfg["steps"] / (ms * 1e-3) / 1e9, 1),
-                                kernel_ms=round(kernel_ms, 5),
-                                kernel_gbs=round(bytes_per_site(codec) * n / (kernel_ms * 1e-3) / 1e9, 1),
+                                gbs_algorithmic=round(bytes_per_site(codec) * nf * cfg["steps"] / (ms * 1e-3) / 1e9, 1),
+                                kernel_ms=round(kernel_ms, 5), kernel_gbs=round(kgbs, 1),
+                                kernel_frac_hbm=round(kgbs / HBM_PEAK_GBS, 4),
+                                shape={k: shape[k] for k in ("variant", "sites_per_thread", "tile_order", "grid")},
                                 finite_totals=bool(np.all(np.isfinite(sums))))
         out[key] = entry
     return out

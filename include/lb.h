@@ -243,8 +243,9 @@ long long lb_steps_done(const lb_lattice *lat);
  * sites, 3 = bytes per stored population, 4 = workgroups per step launch,
  * 5 = x-rows per storage block, 6 = number of fluid sites, 7 = bytes of one
  * population array, 8 = 1 for in-place (one-array) storage, 9 = storage
- * codec, 10 = range widenings of LB_S16 storage so far.  Returns -1 for an
- * unknown key or a bad handle.
+ * codec, 10 = range widenings of LB_S16 storage so far, 11 = tile order (0
+ * linear, 1 a contiguous range of tiles per XCD).  Returns -1 for an unknown
+ * key or a bad handle.
  */
 long long lb_query(const lb_lattice *lat, int key);
 
@@ -261,6 +262,17 @@ int lb_time_steps(lb_lattice *lat, int n, double *ms);
  * in milliseconds in *ms.  The state advances by n steps as with lb_step.
  */
 int lb_time_step_kernel(lb_lattice *lat, int n, double *ms);
+
+/*
+ * Launch-shape tuner: time the step kernel with every vector width that
+ * divides nx (16-, 8- and 4-byte accesses per lane) and both tile orders
+ * (linear, or a contiguous range of tiles per XCD), reps launches each, and
+ * keep the fastest for this lattice (lb_query keys 0 and 4 report it).  Each
+ * timing launch reads the current state and writes the other array, so the
+ * state, the step count and the totals are unchanged.  Synchronises.  Not for
+ * in-place storage (LB_EINVAL).
+ */
+int lb_tune(lb_lattice *lat, int reps);
 
 /*
  * Bandwidth ceiling probe: a streaming copy (one 16-byte non-temporal load

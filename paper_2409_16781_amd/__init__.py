@@ -49,6 +49,7 @@ _SIGNATURES = {
     "lb_query": (ctypes.c_longlong, [_P, ctypes.c_int]),
     "lb_time_steps": (ctypes.c_int, [_P, ctypes.c_int, _P]),
     "lb_time_step_kernel": (ctypes.c_int, [_P, ctypes.c_int, _P]),
+    "lb_tune": (ctypes.c_int, [_P, ctypes.c_int]),
     "lb_copy_probe": (ctypes.c_int, [_P, ctypes.c_int, _P]),
     "lb_set_force_field": (ctypes.c_int, [_P, _P]),
     "lb_grad_force_x": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _P]),
@@ -307,13 +308,19 @@ class Lattice:
     @property
     def info(self) -> dict:
         keys = ["variant", "sites_per_thread", "solids", "bytes_per_population", "grid", "block_rows", "n_fluid",
-                "array_bytes", "inplace", "codec", "rescales"]
+                "array_bytes", "inplace", "codec", "rescales", "tile_order"]
         return {k: self.query(i) for i, k in enumerate(keys)}
 
     def time_steps(self, n: int) -> float:
         ms = ctypes.c_double(0.0)
         _check(lib().lb_time_steps(self._h, int(n), ctypes.byref(ms)), "lb_time_steps")
         return ms.value
+
+    def tune(self, reps: int = 10) -> dict:
+        """Time the step kernel's launch shapes on this lattice and keep the
+        fastest (state unchanged); returns the lattice info."""
+        _check(lib().lb_tune(self._h, int(reps)), "lb_tune")
+        return self.info
 
     def time_step_kernel(self, n: int) -> float:
         """Mean duration (ms) of the step kernel alone over n eager steps."""

@@ -897,14 +897,15 @@ int grad_impl(lb_lattice *h, int nsteps, int every, const float *seed, float *gr
     auto hip = [&](hipError_t e, const char *what) {
         if (rc == LB_OK && e != hipSuccess) rc = fail(LB_EHIP, "%s: %s", what, hipGetErrorString(e));
     };
-    // forward: checkpoints, then the ordinary steps (the lattice ends at step nsteps)
-    for (int n = 0; n < nsteps && rc == LB_OK; ++n) {
-        if (n % every == 0)
-            hip(hipMemcpyAsync(ck[n / every], h->buf[h->cur], abytes, hipMemcpyDeviceToDevice, h->stream), "checkpoint");
-        if (rc == LB_OK) rc = enqueue_one(h, h->cur, nullptr, nullptr, h->stream, own_bufs(h));
+    // forward: a checkpoint, then the segment's ordinary steps as one run
+    // (chained totals); the lattice ends at step nsteps
+    for (int k = 0; k < nck && rc == LB_OK; ++k) {
+        const int len = std::min(every, nsteps - k * every);
+        hip(hipMemcpyAsync(ck[k], h->buf[h->cur], abytes, hipMemcpyDeviceToDevice, h->stream), "checkpoint");
+        if (rc == LB_OK) rc = enqueue_run(h, h->cur, len, h->stream, own_bufs(h));
         if (rc == LB_OK) {
-            h->cur ^= 1;
-            h->steps += 1;
+            h->cur ^= len & 1;
+            h->steps += len;
         }
     }
     // the objective of the final state: J, and its seed in the storage layout
@@ -1138,6 +1139,7 @@ long long lb_query(const lb_lattice *h, int key)
         case 8: return h->inplace ? 1 : 0;
         case 9: return h->codec;
         case 10: return h->rescales;
+        case 11: return h->tile_order;
         default: return -1;
     }
 }
@@ -1160,6 +1162,79 @@ int lb_time_steps(lb_lattice *h, int n, double *ms)
     if (rc == LB_OK) *ms = t;
     if (rc == LB_OK) rc = settle(h);  // scaled storage: redo flagged steps (outside the timed region)
     return rc;
+}
+
+int lb_tune(lb_lattice *h, int reps)
+{
+    if (int rc = check(h)) return rc;
+    if (reps < 1 || reps > 1000) return fail(LB_EINVAL, "reps must be in [1, 1000] (got %d)", reps);
+    if (h->inplace) return fail(LB_EINVAL, "the in-place step has one launch shape per lattice");
+    if (int rc = settle(h)) return rc;
+    // candidates: vector widths that divide nx, each with both tile orders
+    struct Cand {
+        int variant, order, grid;
+        double ms;
+    };
+    std::vector<Cand> cands;
+    int max_grid = h->grid;
+    for (int v = 1; v <= 3; ++v) {
+        const int V = sites_per_thread(h->codec, v);
+        if (h->nx % V != 0) continue;
+        const uint64_t tiles = (h->n / V + kBlock - 1) / kBlock;
+        if (tiles > 0x7fffffffull) continue;
+        for (int order = 0; order < 2; ++order) cands.push_back(Cand{v, order, (int)tiles, 0.0});
+        max_grid = std::max(max_grid, (int)tiles);
+    }
+    if (cands.empty()) return LB_OK;  // only the one-site kernel fits this nx
+    // partials for the largest grid (timing launches, and the choice)
+    if (max_grid > h->grid) {
+        HIP_OR_FAIL(hipStreamSynchronize(h->stream));
+        (void)hipFree(h->partials);
+        (void)hipFree(h->gpartials);
+        h->partials = h->gpartials = nullptr;
+        const size_t ngroups = ((size_t)max_grid + kRedChunk - 1) / kRedChunk;
+        if (hipMalloc(&h->partials, (size_t)max_grid * 8 * sizeof(double)) != hipSuccess ||
+            hipMalloc(&h->gpartials, ngroups * 4 * sizeof(double)) != hipSuccess)
+            return fail(LB_ENOMEM, "hipMalloc(partials)");
+    }
+    // every timing launch reads the current state and writes the other array:
+    // the state, the step count and the totals ring stay as they are
+    Events evs(2);
+    HIP_OR_FAIL(evs.create());
+    const int saved_variant = h->variant, saved_order = h->tile_order;
+    int rc = LB_OK;
+    for (Cand &c : cands) {
+        h->variant = c.variant;
+        h->tile_order = c.order;
+        const StepArgs a = step_args(h, h->cur, nullptr, nullptr, c.variant);
+        for (int k = 0; k < 2 && rc == LB_OK; ++k)  // warm-up
+            if (launch_step(h->codec, c.variant, h->solids, false, a, c.grid, h->stream) != hipSuccess)
+                rc = fail(LB_EHIP, "step kernel launch");
+        if (rc == LB_OK && hipEventRecord(evs[0], h->stream) != hipSuccess) rc = fail(LB_EHIP, "hipEventRecord");
+        for (int k = 0; k < reps && rc == LB_OK; ++k)
+            if (launch_step(h->codec, c.variant, h->solids, false, a, c.grid, h->stream) != hipSuccess)
+                rc = fail(LB_EHIP, "step kernel launch");
+        if (rc == LB_OK && hipEventRecord(evs[1], h->stream) != hipSuccess) rc = fail(LB_EHIP, "hipEventRecord");
+        float t = 0.0f;
+        if (rc == LB_OK && hipEventSynchronize(evs[1]) != hipSuccess) rc = fail(LB_EHIP, "hipEventSynchronize");
+        if (rc == LB_OK && hipEventElapsedTime(&t, evs[0], evs[1]) != hipSuccess) rc = fail(LB_EHIP, "hipEventElapsedTime");
+        c.ms = (double)t / reps;
+        if (rc != LB_OK) break;
+    }
+    h->variant = saved_variant;
+    h->tile_order = saved_order;
+    if (rc != LB_OK) return rc;
+    const Cand *best = &cands[0];
+    for (const Cand &c : cands)
+        if (c.ms < best->ms) best = &c;
+    h->variant = best->variant;
+    h->vsites = sites_per_thread(h->codec, best->variant);
+    h->tile_order = best->order;
+    h->grid = best->grid;
+    h->graphs.invalidate();
+    if (h->codec == kS16) HIP_OR_FAIL(launch_zero_words(h->ovf, 2, h->stream));  // timing launches may flag
+    HIP_OR_FAIL(hipStreamSynchronize(h->stream));
+    return LB_OK;
 }
 
 int lb_time_step_kernel(lb_lattice *h, int n, double *ms)

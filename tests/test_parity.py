@@ -315,6 +315,27 @@ def test_chained_totals_equal_per_step_reduce_on_many_chunks():
     b.close()
 
 
+@pytest.mark.parametrize("codec", ["f32", "f16", "s16"])
+def test_tune_keeps_the_state_and_picks_a_valid_shape(codec):
+    """lb_tune times launch shapes with launches that read the current state
+    and write the other array: state, step count and totals are unchanged,
+    and the lattice then steps on in the chosen shape within the bound."""
+    cfg = inputs.channel(64, 34, 16, tau=0.6, g=1e-5, steps=50, noise=1e-4, seed=1)
+    lat = make_lattice(cfg, codec)
+    lat.step(7)
+    raw, tot = lat.get_f(), lat.sums(7)
+    info = lat.tune(5)
+    say(f"  {codec}: tuned shape variant={info['variant']} tile_order={info['tile_order']} grid={info['grid']}")
+    assert info["variant"] in (1, 2, 3) and info["tile_order"] in (0, 1)
+    assert np.array_equal(lat.get_f(), raw) and np.array_equal(lat.sums(7), tot) and lat.steps_done == 7
+    lat.step(43)
+    _, u = lat.macros()
+    _, u_ref, _ = oracle_run(cfg, 50)
+    err = rel_l2_u(u.double().cpu().numpy(), u_ref, fluid_mask(cfg))
+    assert err <= (1e-5 if codec == "f32" else 2e-3), err
+    lat.close()
+
+
 @pytest.mark.parametrize("codec", ["f32", "f16", "bf16"])
 def test_checkpoint_resume_is_bit_exact(codec):
     cfg = _porous(32, 12, 8, 0.1, 91)
