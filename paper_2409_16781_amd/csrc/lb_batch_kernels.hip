@@ -18,18 +18,18 @@ typedef LB_CONSTANT_AS const int ConstInt;
 __device__ __forceinline__ void append_batch_totals(const BatchTotalsArgs &t)
 {
     const unsigned long long step = __hip_atomic_load(t.step_counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    for (int d = 0; d < t.ndoms; ++d) {
+    // the four waves take domains in turn, each sum in reduce_domains' order
+    for (int d = (int)threadIdx.x >> 6; d < t.ndoms; d += kBlock / 64) {
         const DomDesc &D = t.doms[d];
         double tot[4];
-        block_sum4(t.partials + 4 * (size_t)D.tile_begin, D.ntiles, tot, false);
-        if (threadIdx.x == 0) {
+        wave_sum4(t.partials + 4 * (size_t)D.tile_begin, D.ntiles, tot);
+        if ((threadIdx.x & 63) == 0) {
             double *r = t.ring + 4 * ((size_t)d * kRingCap + step % kRingCap);
             r[0] = D.n_fluid + tot[0];
             r[1] = tot[1];
             r[2] = tot[2];
             r[3] = tot[3];
         }
-        __syncthreads();  // every thread has read the tree root before the next domain rewrites it
     }
     if (threadIdx.x == 0) __hip_atomic_store(t.step_counter, step + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }

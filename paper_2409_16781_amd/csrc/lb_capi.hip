@@ -1197,8 +1197,18 @@ int lb_tune(lb_lattice *h, int reps)
             hipMalloc(&h->gpartials, ngroups * 4 * sizeof(double)) != hipSuccess)
             return fail(LB_ENOMEM, "hipMalloc(partials)");
     }
-    // every timing launch reads the current state and writes the other array:
-    // the state, the step count and the totals ring stay as they are
+    // every timing launch reads the current state and writes the other array,
+    // and, like a step inside a run, its first workgroup appends the totals
+    // of the previous launch (the append's cost grows with the grid) -- into
+    // a ring and counter of the tuner's own: the state, the step count and
+    // the lattice's totals stay as they are
+    double *tring = nullptr;
+    unsigned long long *tctr = nullptr;
+    if (hipMalloc(&tring, 64 * 4 * sizeof(double)) != hipSuccess ||
+        hipMalloc(&tctr, sizeof(unsigned long long)) != hipSuccess) {
+        if (tring) (void)hipFree(tring);
+        return fail(LB_ENOMEM, "hipMalloc(tuner totals)");
+    }
     Events evs(2);
     HIP_OR_FAIL(evs.create());
     const int saved_variant = h->variant, saved_order = h->tile_order;
@@ -1206,14 +1216,26 @@ int lb_tune(lb_lattice *h, int reps)
     for (Cand &c : cands) {
         h->variant = c.variant;
         h->tile_order = c.order;
-        const StepArgs a = step_args(h, h->cur, nullptr, nullptr, c.variant);
-        for (int k = 0; k < 2 && rc == LB_OK; ++k)  // warm-up
+        if (hipMemsetAsync(tctr, 0, sizeof(unsigned long long), h->stream) != hipSuccess) rc = fail(LB_EHIP, "memset");
+        auto launch = [&](int k) {
+            StepArgs a = step_args(h, h->cur, nullptr, nullptr, c.variant);
+            a.partials = h->partials + (size_t)(k & 1) * 4 * c.grid;
+            if (k > 0) {
+                TotalsArgs t{};
+                t.partials = h->partials + (size_t)((k - 1) & 1) * 4 * c.grid;
+                t.nparts = c.grid;
+                t.gpartials = h->gpartials;
+                t.ring = tring;
+                t.step_counter = tctr;
+                t.n_fluid = h->n_fluid;
+                a.prev = t;
+            }
             if (launch_step(h->codec, c.variant, h->solids, false, a, c.grid, h->stream) != hipSuccess)
                 rc = fail(LB_EHIP, "step kernel launch");
+        };
+        for (int k = 0; k < 2 && rc == LB_OK; ++k) launch(k);  // warm-up
         if (rc == LB_OK && hipEventRecord(evs[0], h->stream) != hipSuccess) rc = fail(LB_EHIP, "hipEventRecord");
-        for (int k = 0; k < reps && rc == LB_OK; ++k)
-            if (launch_step(h->codec, c.variant, h->solids, false, a, c.grid, h->stream) != hipSuccess)
-                rc = fail(LB_EHIP, "step kernel launch");
+        for (int k = 2; k < reps + 2 && rc == LB_OK; ++k) launch(k);
         if (rc == LB_OK && hipEventRecord(evs[1], h->stream) != hipSuccess) rc = fail(LB_EHIP, "hipEventRecord");
         float t = 0.0f;
         if (rc == LB_OK && hipEventSynchronize(evs[1]) != hipSuccess) rc = fail(LB_EHIP, "hipEventSynchronize");
@@ -1221,6 +1243,9 @@ int lb_tune(lb_lattice *h, int reps)
         c.ms = (double)t / reps;
         if (rc != LB_OK) break;
     }
+    (void)hipStreamSynchronize(h->stream);
+    (void)hipFree(tring);
+    (void)hipFree(tctr);
     h->variant = saved_variant;
     h->tile_order = saved_order;
     if (rc != LB_OK) return rc;

@@ -480,14 +480,24 @@ __device__ __forceinline__ void collide(float (&g)[kQ], const Coll &p, float &rh
 
 // Per-direction totals -> {mass deviation, momentum} of a group of sites
 // (FP32 for the macroscopic fields, FP64 for the conservation totals).
+// Sums and differences of the nine opposite pairs first (18 additions), then
+// the mass (9 more) and the three momentum components (4 each).
 template <typename T>
 __device__ __forceinline__ void moments_of_totals(const T (&t)[kQ], T &m, T &px, T &py, T &pz)
 {
-    m = t[0] + ((t[1] + t[2]) + (t[3] + t[4])) + ((t[5] + t[6]) + (t[7] + t[8])) + ((t[9] + t[10]) + (t[11] + t[12])) +
-        ((t[13] + t[14]) + (t[15] + t[16])) + (t[17] + t[18]);
-    px = (t[1] - t[2]) + (t[7] + t[8]) - (t[9] + t[10]) + (t[11] + t[12]) - (t[13] + t[14]);
-    py = (t[3] - t[4]) + (t[7] - t[8]) + (t[9] - t[10]) + (t[15] + t[16]) - (t[17] + t[18]);
-    pz = (t[5] - t[6]) + (t[11] - t[12]) + (t[13] - t[14]) + (t[15] - t[16]) + (t[17] - t[18]);
+    const T s1 = t[1] + t[2], d1 = t[1] - t[2];
+    const T s3 = t[3] + t[4], d3 = t[3] - t[4];
+    const T s5 = t[5] + t[6], d5 = t[5] - t[6];
+    const T s7 = t[7] + t[10], d7 = t[7] - t[10];     // (+1, +1, 0) / (-1, -1, 0)
+    const T s8 = t[8] + t[9], d8 = t[8] - t[9];       // (+1, -1, 0) / (-1, +1, 0)
+    const T s11 = t[11] + t[14], d11 = t[11] - t[14]; // (+1, 0, +1) / (-1, 0, -1)
+    const T s12 = t[12] + t[13], d12 = t[12] - t[13]; // (+1, 0, -1) / (-1, 0, +1)
+    const T s15 = t[15] + t[18], d15 = t[15] - t[18]; // (0, +1, +1) / (0, -1, -1)
+    const T s16 = t[16] + t[17], d16 = t[16] - t[17]; // (0, +1, -1) / (0, -1, +1)
+    m = t[0] + (((s1 + s3) + (s5 + s7)) + ((s8 + s11) + (s12 + s15))) + s16;
+    px = ((d1 + d7) + (d8 + d11)) + d12;
+    py = ((d3 + d7) - (d8 - d15)) + d16;
+    pz = ((d5 + d11) - (d12 - d15)) - d16;
 }
 
 // FP64 totals of the values a lane stores: every stored element is converted
@@ -500,29 +510,23 @@ __device__ __forceinline__ void add_lane_totals(const Lane<NW> (&d)[kQ], double 
 {
     using K = Codec<C>;
     constexpr int V = NW * 4 / K::kBytes;
-    double m = 0.0, px = 0.0, py = 0.0, pz = 0.0;
+    double t[kQ];
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
-        double t;
         if constexpr (C == kS16) {
             // integer codes sum exactly; one exact scaling by 2^-e_i
             int qs = (int16_t)(uint16_t)vget<C, NW>(d[i], 0);
 #pragma unroll
             for (int e = 1; e < V; ++e) qs += (int16_t)(uint16_t)vget<C, NW>(d[i], e);
-            t = (double)qs * (double)sc.dm[weight_class(i)];
+            t[i] = (double)qs * (double)sc.dm[weight_class(i)];
         } else {
-            t = (double)K::dec(vget<C, NW>(d[i], 0));
+            t[i] = (double)K::dec(vget<C, NW>(d[i], 0));
 #pragma unroll
-            for (int e = 1; e < V; ++e) t += (double)K::dec(vget<C, NW>(d[i], e));
+            for (int e = 1; e < V; ++e) t[i] += (double)K::dec(vget<C, NW>(d[i], e));
         }
-        m += t;
-        if (CX[i] > 0) px += t;
-        if (CX[i] < 0) px -= t;
-        if (CY[i] > 0) py += t;
-        if (CY[i] < 0) py -= t;
-        if (CZ[i] > 0) pz += t;
-        if (CZ[i] < 0) pz -= t;
     }
+    double m, px, py, pz;
+    moments_of_totals(t, m, px, py, pz);
     acc[0] += m;
     acc[1] += px;
     acc[2] += py;
@@ -538,22 +542,24 @@ __device__ __forceinline__ void add_lane_totals(const Lane<NW> (&d)[kQ], double 
 
 __device__ __forceinline__ void store_block_totals(const double (&acc)[4], double *out)
 {
-    __shared__ double red[4][kBlock];
+    // a butterfly within each wave, then the four wave sums through 128 bytes
+    // of LDS (a small footprint keeps more workgroups resident per CU)
+    __shared__ double red[kBlock / 64][4];
+    double v[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = acc[k];
+    for (int k = 0; k < 4; ++k) {
+        v[k] = acc[k];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) red[threadIdx.x >> 6][k] = v[k];
+    }
     __syncthreads();
-    if (threadIdx.x < 64) {
-        double v[4];
+    if (threadIdx.x == 0) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            v[k] = (red[k][threadIdx.x] + red[k][threadIdx.x + 64]) + (red[k][threadIdx.x + 128] + red[k][threadIdx.x + 192]);
-#pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
-        }
-        if (threadIdx.x == 0) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) out[k] = v[k];
-        }
+        for (int k = 0; k < 4; ++k) out[k] = (red[0][k] + red[1][k]) + (red[2][k] + red[3][k]);
     }
 }
 
@@ -581,24 +587,66 @@ __device__ __forceinline__ void block_sum4(const double *v, int count, double (&
     for (int k = 0; k < 4; ++k) out[k] = tot[k][0];
 }
 
+// block_sum4's sum computed by one wave alone, in exactly the same order
+// (bitwise the same result, valid in lane 0): lane l plays the threads l,
+// l + 64, l + 128 and l + 192 of the block (each first summing its strided
+// values), forms the tree's first two levels in registers, and takes the six
+// remaining levels with shuffles from the lane w above (no barriers).
+__device__ __forceinline__ void wave_sum4(const double *v, int count, double (&out)[4])
+{
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const int lane = threadIdx.x & 63;
+    double a[4][4];  // [block thread l + 64 q][component]
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) a[q][k] = 0.0;
+    // one pass per 256 partials; the four threads' loads of a pass are
+    // independent and issued together (32 bytes each)
+    for (int base = 0; base < count; base += kBlock) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int b = base + lane + 64 * q;
+            if (b < count) {
+                const d2 lo = *reinterpret_cast<const d2 *>(v + 4 * (size_t)b);
+                const d2 hi = *reinterpret_cast<const d2 *>(v + 4 * (size_t)b + 2);
+                a[q][0] += lo[0];
+                a[q][1] += lo[1];
+                a[q][2] += hi[0];
+                a[q][3] += hi[1];
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double x = (a[0][k] + a[2][k]) + (a[1][k] + a[3][k]);
+#pragma unroll
+        for (int w = 32; w >= 1; w >>= 1) x += __shfl_down(x, w, 64);
+        out[k] = x;
+    }
+}
+
 // The totals of one step from its workgroup partials t.partials, summed by a
 // single workgroup in the order of reduce_totals (each chunk of kRedChunk
 // partials, then the chunk sums, both in the same fixed trees, so the result
-// is bitwise the same) and appended to the ring.  The partials were written
-// by an earlier launch, so no fence is needed before reading them.
+// is bitwise the same) and appended to the ring.  The four waves take
+// chunks in turn.  The partials were written by an earlier launch, so no
+// fence is needed before reading them.
 __device__ __forceinline__ void append_step_totals(const TotalsArgs &t)
 {
     const int nchunks = (t.nparts + kRedChunk - 1) / kRedChunk;
-    for (int c = 0; c < nchunks; ++c) {
+    for (int c = (int)threadIdx.x >> 6; c < nchunks; c += kBlock / 64) {
         double gs[4];
-        block_sum4(t.partials + 4 * (size_t)c * kRedChunk, min(kRedChunk, t.nparts - c * kRedChunk), gs, false);
-        if (threadIdx.x == 0) {
+        wave_sum4(t.partials + 4 * (size_t)c * kRedChunk, min(kRedChunk, t.nparts - c * kRedChunk), gs);
+        if ((threadIdx.x & 63) == 0) {
 #pragma unroll
             for (int k = 0; k < 4; ++k)
                 __hip_atomic_store(&t.gpartials[4 * c + k], gs[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        __syncthreads();  // every thread has read the tree root before the next chunk rewrites it
     }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __syncthreads();  // every wave's chunk sums are stored
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     double tot[4];
     block_sum4(t.gpartials, nchunks, tot, true);
     if (threadIdx.x == 0) {
@@ -817,13 +865,12 @@ __device__ __forceinline__ uint32_t gather(const StepArgs &a, const char *src, c
     }
 #pragma unroll
     for (int i = 0; i < kQ; ++i) d[i] = ldv<NW, !kSolids>(src + (rb[i] + x0) * K::kBytes);
-    // Lattices: waves with a dead site or a bounce-back issue their
-    // neighbour masks right behind the pulls, the others read no mask at all.
-    // Batches (porous domains, nearly every wave dirty): a dirty byte per row,
-    // checked per lane once the pulls are in.
+    // Waves with a dead site or a bounce-back issue their neighbour masks
+    // right behind the pulls (one round trip for both); the others read no
+    // mask at all.
     bool dirty = false;
     uint32_t m[V];
-    if constexpr (kSolids && !kPadded) {
+    if constexpr (kSolids) {
         dirty = wave_dirty(a, g);
         if (dirty) load_masks<V>(a.nbmask + g.s0, m);
     }
@@ -905,10 +952,6 @@ __device__ __forceinline__ uint32_t gather(const StepArgs &a, const char *src, c
         for (int e = 1; e < V; ++e) dead |= (x0 + e >= nx ? 1u : 0u) << e;
     }
     if constexpr (kSolids) {
-        if constexpr (kPadded) {
-            dirty = a.rowdirty[g.row] != 0;
-            if (dirty) load_masks<V>(a.nbmask + g.s0, m);
-        }
         if (dirty) {
 #pragma unroll
             for (int e = 0; e < V; ++e) dead |= (m[e] >> 31) << e;
