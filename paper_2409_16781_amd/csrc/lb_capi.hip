@@ -714,7 +714,10 @@ int lb_init_eq(lb_lattice *h, const double *rho, const double *u)
             float mx = 0.0f;
             std::memcpy(&mx, &bits[c], sizeof mx);
             if (!std::isfinite(mx)) return fail(LB_EINVAL, "initial fields are not finite");
-            // at rest (mx = 0) the class gets |g| <= w / 16
+            // one bit of headroom; at rest (mx = 0) the class gets |g| <= w / 16.
+            // (Four bits for the rest population would avoid the widenings of
+            // the first steps from a noisy velocity field, but its coarser step
+            // then costs more accuracy than the widenings cost time.)
             int m = mx > 0.0f ? (int)std::ceil(std::log2(2.0 * (double)mx)) : -4;
             m = std::min(3, std::max(-30, m));
             h->s16e[c] = s16_class_exponent(c, m);
@@ -1155,12 +1158,13 @@ int lb_time_steps(lb_lattice *h, int n, double *ms)
     int rc = LB_OK;
     if (hipEventRecord(e0, h->stream) != hipSuccess) rc = fail(LB_EHIP, "hipEventRecord");
     if (rc == LB_OK) rc = enqueue_steps(h, n, nullptr, nullptr);
+    // scaled storage: steps redone after a widening count in the timed region
+    if (rc == LB_OK) rc = settle(h);
     if (rc == LB_OK && hipEventRecord(e1, h->stream) != hipSuccess) rc = fail(LB_EHIP, "hipEventRecord");
     if (rc == LB_OK && hipEventSynchronize(e1) != hipSuccess) rc = fail(LB_EHIP, "hipEventSynchronize");
     float t = 0.0f;
     if (rc == LB_OK && hipEventElapsedTime(&t, e0, e1) != hipSuccess) rc = fail(LB_EHIP, "hipEventElapsedTime");
     if (rc == LB_OK) *ms = t;
-    if (rc == LB_OK) rc = settle(h);  // scaled storage: redo flagged steps (outside the timed region)
     return rc;
 }
 

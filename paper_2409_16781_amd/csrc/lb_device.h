@@ -500,6 +500,26 @@ __device__ __forceinline__ void moments_of_totals(const T (&t)[kQ], T &m, T &px,
     pz = ((d5 + d11) - (d12 - d15)) - d16;
 }
 
+// Mass and momentum per weight class (rest, axis, diagonal) of integer
+// per-population sums t (exact in integers; the rest class has no momentum).
+__device__ __forceinline__ void moments_of_totals_by_class(const int (&t)[kQ], int (&m)[3], int (&px)[3], int (&py)[3],
+                                                           int (&pz)[3])
+{
+    const int d1 = t[1] - t[2], d3 = t[3] - t[4], d5 = t[5] - t[6];
+    const int d7 = t[7] - t[10], d8 = t[8] - t[9], d11 = t[11] - t[14];
+    const int d12 = t[12] - t[13], d15 = t[15] - t[18], d16 = t[16] - t[17];
+    m[0] = t[0];
+    m[1] = (t[1] + t[2]) + (t[3] + t[4]) + (t[5] + t[6]);
+    m[2] = ((t[7] + t[10]) + (t[8] + t[9])) + ((t[11] + t[14]) + (t[12] + t[13])) + ((t[15] + t[18]) + (t[16] + t[17]));
+    px[0] = py[0] = pz[0] = 0;
+    px[1] = d1;
+    py[1] = d3;
+    pz[1] = d5;
+    px[2] = (d7 + d8) + (d11 + d12);
+    py[2] = (d7 - d8) + (d15 + d16);
+    pz[2] = (d11 - d12) + (d15 - d16);
+}
+
 // FP64 totals of the values a lane stores: every stored element is converted
 // to double and summed per direction, then the directions are combined into
 // {mass deviation, momentum}, all in FP64 and in a fixed order (dead
@@ -510,23 +530,36 @@ __device__ __forceinline__ void add_lane_totals(const Lane<NW> (&d)[kQ], double 
 {
     using K = Codec<C>;
     constexpr int V = NW * 4 / K::kBytes;
-    double t[kQ];
+    double m, px, py, pz;
+    if constexpr (C == kS16) {
+        // The codes are integers: the lane's mass and momentum per weight
+        // class are exact int32 sums (|sum| < 12 V 2^15), each scaled once by
+        // its class's 2^-e (exact in double); only the few class terms are
+        // added in FP64.
+        int q[kQ];
 #pragma unroll
-    for (int i = 0; i < kQ; ++i) {
-        if constexpr (C == kS16) {
-            // integer codes sum exactly; one exact scaling by 2^-e_i
-            int qs = (int16_t)(uint16_t)vget<C, NW>(d[i], 0);
+        for (int i = 0; i < kQ; ++i) {
+            q[i] = (int16_t)(uint16_t)vget<C, NW>(d[i], 0);
 #pragma unroll
-            for (int e = 1; e < V; ++e) qs += (int16_t)(uint16_t)vget<C, NW>(d[i], e);
-            t[i] = (double)qs * (double)sc.dm[weight_class(i)];
-        } else {
+            for (int e = 1; e < V; ++e) q[i] += (int16_t)(uint16_t)vget<C, NW>(d[i], e);
+        }
+        int qm[3], qx[3], qy[3], qz[3];
+        moments_of_totals_by_class(q, qm, qx, qy, qz);
+        const double s0 = (double)sc.dm[0], s1 = (double)sc.dm[1], s2 = (double)sc.dm[2];
+        m = ((double)qm[0] * s0 + (double)qm[1] * s1) + (double)qm[2] * s2;
+        px = (double)qx[1] * s1 + (double)qx[2] * s2;
+        py = (double)qy[1] * s1 + (double)qy[2] * s2;
+        pz = (double)qz[1] * s1 + (double)qz[2] * s2;
+    } else {
+        double t[kQ];
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) {
             t[i] = (double)K::dec(vget<C, NW>(d[i], 0));
 #pragma unroll
             for (int e = 1; e < V; ++e) t[i] += (double)K::dec(vget<C, NW>(d[i], e));
         }
+        moments_of_totals(t, m, px, py, pz);
     }
-    double m, px, py, pz;
-    moments_of_totals(t, m, px, py, pz);
     acc[0] += m;
     acc[1] += px;
     acc[2] += py;

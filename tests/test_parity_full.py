@@ -4,9 +4,12 @@
   as the nz = 1 lattice (every site does the same arithmetic; the oracle
   checks this bit for bit), so the whole 512^3 field is compared with an FP64
   oracle run on 512 x 512 x 1 sites.
-* 512^3 Taylor-Green vortex with seeded U(+-1e-3) velocity noise: sampled
-  sites after 16 steps against the light-cone oracle (a site after n steps
-  depends only on the initial state within distance n).
+* 512^3 Taylor-Green vortex with seeded U(+-1e-3) velocity noise (the timed
+  workload): sampled sites after 16 steps against the light-cone oracle (a
+  site after n steps depends only on the initial state within distance n),
+  and after 200 and 1000 steps against stored FP64 oracle results of the
+  whole run (16384 seeded sites, plus whole-field mode amplitude, energy and
+  mass), for FP32, FP16, scaled 16-bit and BF16 storage.
 * 256 x 128 x 128 channel, 5000 steps: sampled sites, the x-z averaged
   profile and the conservation totals against stored FP64 oracle results
   (tests/golden/channel256x128x128_5000.json, written by
@@ -14,9 +17,9 @@
 * Largest lattices: 1280^3 (2.1e9 sites, near the 2^31-site index limit) with
   FP16 storage and 1024^3 with FP32 storage, sampled sites after 4 steps.
 
-Bounds: relative L2 error of u <= 1e-5 (FP32 storage) and <= 2e-3 (FP16);
-BF16 storage is held to the same 2e-3 bound as FP16 and fails it (an expected
-failure, with the measured error).
+Bounds: relative L2 error of u <= 1e-5 (FP32 storage) and <= 2e-3 (FP16 and
+scaled 16-bit); BF16 storage is held to the same 2e-3 bound and fails it (an
+expected failure, with the measured error).
 """
 import json
 import math
