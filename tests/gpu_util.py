@@ -2,6 +2,7 @@
 binding) and through the oracle, and compare."""
 from __future__ import annotations
 
+import math
 import os
 import sys
 from contextlib import contextmanager
@@ -152,6 +153,21 @@ FP64_SUM_TOL = 64 * 2.0 ** -53
 
 # D3Q19 weights in the same order (the stored value is g = f - w).
 W19 = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12, dtype=np.float64)
+
+
+def streamed_pair(g_gpu, g0, steps, flags=None):
+    """Pure streaming (omega = 0, F = 0) check values: the oracle's state
+    after `steps` steps from the unshifted f = g0 + w, and the GPU's stored
+    values g_gpu unshifted the same way.  At omega = 0 both sides only move
+    values (bounce-back keeps the weight class), so fl(g + w) is formed from
+    the same g at the same w on each side and the two arrays are equal bit
+    for bit.  (Handing the oracle g itself would give it densities near 0,
+    and u = m / rho is 0 / 0 at a site whose stored values cancel.)"""
+    import oracle
+
+    w = W19.reshape((19,) + (1,) * (g0.ndim - 1))
+    ref = oracle.run(g0 + w, math.inf, steps, flags=flags)
+    return g_gpu + w, ref
 
 
 def totals_gap_bound(g_gpu, S_oracle, mask):

@@ -14,7 +14,7 @@ import oracle
 import paper_2409_16781_amd as lbm
 from paper_2409_16781_amd import inputs
 from gpu_util import (FP64_SUM_TOL, TOL_U_BF16, bf16_bound, decode_raw, exact_state_totals, fluid_mask, gpu_run,
-                      make_lattice, max_abs, oracle_run, rel_l2_u, require_gpu, say, totals_gap_bound)
+                      make_lattice, max_abs, oracle_run, rel_l2_u, require_gpu, say, streamed_pair, totals_gap_bound)
 
 pytestmark = pytest.mark.gpu
 
@@ -128,10 +128,13 @@ def _random_raw(shape, codec, seed):
 @pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("codec", ["f32", "f16", "bf16"])
 @pytest.mark.parametrize("walls", [False, True])
-def test_pure_streaming_bit_exact(codec, variant, walls):
+@pytest.mark.parametrize("shape", [(6, 10, 32), (3, 4, 512), (2, 3, 1536)])
+def test_pure_streaming_bit_exact(codec, variant, walls, shape):
     """omega = 0 (tau = inf), F = 0: three steps permute the stored values;
-    the GPU result equals the oracle's permutation of the same values exactly."""
-    shape = (6, 10, 32)
+    the GPU result equals the oracle's permutation of the same values exactly.
+    At nx = 512 and 1536 every wave of the vector-row kernels lies inside one
+    row (the kernels with wave-uniform row addressing); at nx = 32 a wave
+    spans several rows."""
     nz, ny, nx = shape
     flags = inputs.random_flags(nx, ny, nz, 0.2, 51) if walls else None
     raw = _random_raw(shape, codec, 52)
@@ -140,8 +143,7 @@ def test_pure_streaming_bit_exact(codec, variant, walls):
     lat = make_lattice(with_variant, codec, variant)
     lat.set_f(raw)
     lat.step(3)
-    out = lbm.decode_state(lat.get_f(), codec)
-    ref = oracle.run(g, math.inf, 3, flags=flags)
+    out, ref = streamed_pair(lbm.decode_state(lat.get_f(), codec), g, 3, flags)
     m = np.ones(shape, bool) if flags is None else flags == 0
     assert np.array_equal(out[:, m], ref[:, m])
 
@@ -162,15 +164,11 @@ def test_sparse_solids_streaming_bit_exact(shape, codec, variant):
     flags[nz - 1, ny - 1, nx - 1] = 1
     flags[2, 3, : max(1, nx // 3)] = 1
     raw = _random_raw(shape, codec, 53)
-    # positive values: the oracle forms u = m / rho even at omega = 0, and a
-    # site whose 19 coarse 16-bit values cancel exactly would give NaN there
-    raw = np.abs(raw) if codec == "f32" else raw & np.uint16(0x7FFF)
     g = lbm.decode_state(raw, codec)
     lat = make_lattice(dict(name="sparse", shape=shape, tau=math.inf, flags=flags), codec, variant)
     lat.set_f(raw)
     lat.step(3)
-    out = lbm.decode_state(lat.get_f(), codec)
-    ref = oracle.run(g, math.inf, 3, flags=flags)
+    out, ref = streamed_pair(lbm.decode_state(lat.get_f(), codec), g, 3, flags)
     m = flags == 0
     assert np.array_equal(out[:, m], ref[:, m])
 

@@ -24,7 +24,7 @@ import oracle
 import paper_2409_16781_amd as lbm
 from paper_2409_16781_amd import inputs
 from gpu_util import (FP64_SUM_TOL, decode_raw, exact_state_totals, fluid_mask, gpu_run, make_lattice, oracle_run,
-                      rel_l2_u, require_gpu, say)
+                      rel_l2_u, require_gpu, say, streamed_pair)
 
 pytestmark = pytest.mark.gpu
 
@@ -91,9 +91,10 @@ def test_ragged_shapes_parity(shape):
 
 @pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("walls", [False, True])
-def test_pure_streaming_bit_exact(variant, walls):
-    """omega = 0, F = 0: three steps permute the stored codes exactly."""
-    shape = (6, 10, 32)
+@pytest.mark.parametrize("shape", [(6, 10, 32), (3, 4, 512)])
+def test_pure_streaming_bit_exact(variant, walls, shape):
+    """omega = 0, F = 0: three steps permute the stored codes exactly (at
+    nx = 512 with wave-uniform row addressing)."""
     nz, ny, nx = shape
     flags = inputs.random_flags(nx, ny, nz, 0.2, 51) if walls else None
     lat = make_lattice(dict(name="omega0", shape=shape, tau=math.inf, flags=flags), "s16", variant)
@@ -103,8 +104,7 @@ def test_pure_streaming_bit_exact(variant, walls):
         raw[:, flags == 1] = 0
     lat.set_f(raw)
     lat.step(3)
-    out = lbm.decode_state(lat.get_f(), "s16", exps)
-    ref = oracle.run(lbm.decode_state(raw, "s16", exps), math.inf, 3, flags=flags)
+    out, ref = streamed_pair(lbm.decode_state(lat.get_f(), "s16", exps), lbm.decode_state(raw, "s16", exps), 3, flags)
     m = np.ones(shape, bool) if flags is None else flags == 0
     assert np.array_equal(out[:, m], ref[:, m])
     assert lat.info["rescales"] == 0
