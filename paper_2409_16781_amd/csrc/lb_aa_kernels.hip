@@ -86,7 +86,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(aa_waves
     char *F = reinterpret_cast<char *>(a.dst);
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     const int ntiles = (a.nslots + kBlock - 1) / kBlock;
-    for (int b = blockIdx.x; b < ntiles; b += gridDim.x) {
+    if (const int b = blockIdx.x; b < ntiles) {  // one workgroup per tile
         const TileGeom g = tile_geom<V, false>(a, tile_of(b, ntiles, a.tile_order));
         Lane<NW> d[kQ];
 #pragma unroll
@@ -149,7 +149,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(push_wav
     const int wave = threadIdx.x >> 6;
     const int rit = (int)threadIdx.x >> a.lg_row_lanes;
     const int ntiles = (a.nslots + kBlock - 1) / kBlock;
-    for (int b = blockIdx.x; b < ntiles; b += gridDim.x) {
+    if (const int b = blockIdx.x; b < ntiles) {  // one workgroup per tile
         const TileGeom g = tile_geom<V, false>(a, tile_of(b, ntiles, a.tile_order));
         Lane<NW> d[kQ];
         const uint32_t dead = gather<C, NW, kSolids, false, true>(a, F, g, d, lds);

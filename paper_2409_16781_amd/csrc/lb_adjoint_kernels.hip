@@ -38,7 +38,7 @@ __global__ __launch_bounds__(kBlock) void adjoint_vec(AdjArgs a)
     const char *lam_src = reinterpret_cast<const char *>(a.lam_in);
     char *nu_out = reinterpret_cast<char *>(a.nu_out);
     const int ntiles = (sa.nslots + kBlock - 1) / kBlock;
-    for (int b = blockIdx.x; b < ntiles; b += gridDim.x) {
+    if (const int b = blockIdx.x; b < ntiles) {  // one workgroup per tile
         const TileGeom g = tile_geom<V, false>(sa, b);
         Lane<NW> d[kQ];
         const uint32_t dead = gather<kF32, NW, kSolids, false, false>(sa, state, g, d, lds);

@@ -502,14 +502,13 @@ int create_impl(lb_lattice **out, int nx, int ny, int nz, double tau, const uint
     h->n_fluid = (double)(n - nsolid);
     h->inplace = inplace;
 
-    // Step kernel: vector rows with 16-byte (FP32) or 8-byte (16-bit codecs)
-    // accesses, 4 sites per lane; narrower vectors when nx is not a multiple
-    // of 4, one site per thread when no vector width divides nx.
-    // LB_KERNEL (0..3) overrides the choice for tuning.
+    // Step kernel: vector rows with 16-byte accesses (FP32: 4 sites per lane,
+    // FP16/BF16: 8) or, for the scaled 16-bit codec, 8-byte accesses (4
+    // sites: its 16-byte kernel runs at two waves per SIMD); narrower vectors
+    // when nx is not a multiple of the width, one site per thread when no
+    // vector width divides nx.  LB_KERNEL (0..3) overrides the choice.
     const long kernel = env_long("LB_KERNEL", -1);
-    // scaled 16-bit storage: 4-byte vectors (two sites per lane) keep its
-    // decode and encode within four waves per SIMD without spills
-    int variant = storage == LB_F32 ? 1 : (storage == LB_S16 ? 3 : 2);
+    int variant = storage == LB_S16 ? 2 : 1;
     if (kernel >= 0 && kernel <= 3) variant = (int)kernel;
     else if (kernel != -1) {
         delete h;
@@ -584,14 +583,12 @@ int create_impl(lb_lattice **out, int nx, int ny, int nz, double tau, const uint
         delete h;
         return rc;
     }
-    // One workgroup per tile of kBlock lanes.  LB_WG_PER_CU caps the grid at
-    // that many workgroups per compute unit (each then loops over tiles).
+    // One workgroup per tile of kBlock lanes (the vector-row step kernels
+    // take exactly one tile each: nothing is carried from tile to tile, which
+    // keeps their register budget to one tile's values).  n <= 2^31 sites, so
+    // the tile count fits the grid.
     const uint64_t tiles = (n / h->vsites + kBlock - 1) / kBlock;
-    uint64_t grid = tiles;
-    const long wg_per_cu = env_long("LB_WG_PER_CU", 0);
-    if (wg_per_cu > 0 && (uint64_t)h->cus * wg_per_cu < grid) grid = (uint64_t)h->cus * wg_per_cu;
-    if (grid > 0x7fffffffull) grid = 0x7fffffff;
-    h->grid = (int)(grid < 1 ? 1 : grid);
+    h->grid = (int)(tiles < 1 ? 1 : tiles);
 
     auto bail = [&](int code, const char *what, hipError_t e) {
         release(h);

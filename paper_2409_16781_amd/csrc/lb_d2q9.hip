@@ -188,9 +188,7 @@ lb2d_lattice *lb2d_create(int nx, int ny, double tau, const uint8_t *flags, doub
     h->lay.blk = 9 * h->lay.seg;
     h->arr_elems = ((uint64_t)ny + R - 1) / R * h->lay.blk;
     const uint64_t tiles = (n / h->vsites + kBlock - 1) / kBlock;
-    h->grid = (int)std::min<uint64_t>(tiles, 0x7fffffffull);
-    const long g = env_long("LB_GRID2D", 0);  // workgroups per launch (each loops over tiles), for sweeps
-    if (g >= 1 && (uint64_t)g < tiles) h->grid = (int)g;
+    h->grid = (int)std::min<uint64_t>(tiles, 0x7fffffffull);  // one workgroup per tile
 
     auto bail = [&](int code, const char *what, hipError_t e) -> lb2d_lattice * {
         release2(h);

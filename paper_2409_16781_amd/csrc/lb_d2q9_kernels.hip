@@ -63,7 +63,7 @@ __global__ __launch_bounds__(kBlock) void step2d(Step2Args a)
     const int rit = (int)threadIdx.x >> a.lg_row_lanes;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     const int ntiles = (a.nslots + kBlock - 1) / kBlock;
-    for (int b = blockIdx.x; b < ntiles; b += gridDim.x) {
+    if (const int b = blockIdx.x; b < ntiles) {  // one workgroup per tile
         const int slot = b * kBlock + (int)threadIdx.x;
         const bool active = slot < a.nslots;
         const uint32_t s0 = (uint32_t)(active ? slot : a.nslots - 1) * V;

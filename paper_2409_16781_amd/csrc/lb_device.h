@@ -256,14 +256,13 @@ struct Codec<kBF16> {
 // float 2^23 (exact), then one FMA applies the scale; encoding is one FMA
 // that lands on the integer grid of [2^23, 2^24) (round to nearest even) and
 // keeps the low 16 bits, back in two's complement.  A value whose code falls
-// outside [-2^15, 2^15) shows as a float outside [2^23, 2^23 + 2^16); the
-// step kernels track the extremes and flag such a step.
+// outside [-2^15, 2^15) shows as a float outside [2^23, 2^23 + 2^16), i.e.
+// one whose upper 16 bits are not 0x4B00 (NaN and infinities included); the
+// step kernels OR those bits together and flag such a step.
 template <>
 struct Codec<kS16> {
     static constexpr int kBytes = 2;
     static constexpr float kBias = 8421376.0f;  // 2^23 + 2^15
-    static constexpr float kLo = 8388608.0f;     // 2^23: code -2^15
-    static constexpr float kHi = 8454143.0f;     // 2^23 + 2^16 - 1: code 2^15 - 1
     // word (zero-extended) -> the float 2^23 + 2^15 + q
     __device__ static float biased(uint32_t b) { return __builtin_bit_cast(float, ((b & 0xffffu) ^ 0x8000u) + 0x4B000000u); }
     // float on the integer grid of [2^23, 2^24) -> word
@@ -282,21 +281,23 @@ __device__ __forceinline__ float dec_at(uint32_t b, const Scale16 &sc, int i)
         return Codec<C>::dec(b);
 }
 
-// Extremes of the biased kS16 codes per weight class, tracked while encoding
-// and tested once per lane.
+// Range test of the biased kS16 codes per weight class, accumulated while
+// encoding and read once per lane: the OR of (bits XOR 0x4B000000) over the
+// class's codes has zero upper bits exactly when every code was in range and
+// finite (one 3-input logic op per value).
 struct Range16 {
-    float lo[3], hi[3];
+    uint32_t o[3];
     __device__ Range16()
     {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) lo[c] = hi[c] = 8421376.0f;  // the code of zero
+        for (int c = 0; c < 3; ++c) o[c] = 0u;
     }
-    // bit c: a code of weight class c left [-2^15, 2^15)
+    // bit c: a code of weight class c left [-2^15, 2^15) or was not finite
     __device__ uint32_t out_bits() const
     {
         uint32_t b = 0;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) b |= (lo[c] >= 8388608.0f && hi[c] <= 8454143.0f) ? 0u : (1u << c);
+        for (int c = 0; c < 3; ++c) b |= (o[c] >> 16) ? (1u << c) : 0u;
         return b;
     }
 };
@@ -308,8 +309,7 @@ __device__ __forceinline__ uint32_t enc_at(float v, const Scale16 &sc, int i, Ra
     if constexpr (C == kS16) {
         const int c = weight_class(i);
         const float f = fmaf(v, sc.em[c], Codec<kS16>::kBias);
-        r.lo[c] = fminf(r.lo[c], f);
-        r.hi[c] = fmaxf(r.hi[c], f);
+        r.o[c] |= __builtin_bit_cast(uint32_t, f) ^ 0x4B000000u;
         return Codec<kS16>::word(f);
     } else {
         return Codec<C>::enc(v);
@@ -1036,17 +1036,23 @@ __device__ __forceinline__ Coll coll_at(const Coll &p, float fx)
     return q;
 }
 
-// kS16: a lane whose codes left their class's range, or one of whose sites
-// has a density that is not finite (the fixed point would hide a NaN), flags
-// the step with the classes to widen (all three for a non-finite density);
-// the step is redone from its intact source array with wider ranges.
-template <int V>
-__device__ __forceinline__ void s16_flag(const StepArgs &a, const Range16 &r, const float (&rho)[V])
+// kS16: a lane whose codes left their class's range, or were not finite (a
+// blown-up site: the fixed point would hide a NaN), flags the step with the
+// classes to widen; the step is redone from its intact source array with
+// wider ranges.
+__device__ __forceinline__ void s16_flag(const StepArgs &a, const Range16 &r)
 {
-    uint32_t bits = r.out_bits();
+    const uint32_t bits = r.out_bits();
+    // one atomic per wave at most, and none once the word holds the bits: a
+    // step in which millions of codes overflow must not serialise on them
+    uint32_t wbits = 0;
 #pragma unroll
-    for (int e = 0; e < V; ++e) bits |= fabsf(rho[e]) < 1e30f ? 0u : 7u;
-    if (bits) __hip_atomic_fetch_or(&a.ovf[a.par], bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int c = 0; c < 3; ++c) wbits |= __ballot((bits >> c) & 1u) != 0 ? (1u << c) : 0u;
+    const unsigned long long active = __ballot(1);
+    if (wbits && (uint32_t)(threadIdx.x & 63) == (uint32_t)__builtin_ctzll(active)) {
+        const uint32_t have = __hip_atomic_load(&a.ovf[a.par], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((have & wbits) != wbits) __hip_atomic_fetch_or(&a.ovf[a.par], wbits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
 // One tile (kBlock lanes, V sites each) of lattice a: gather with periodic
@@ -1070,7 +1076,7 @@ __device__ __forceinline__ void tile_update(const StepArgs &a, const char *src, 
 
     // collide site by site (16-bit codecs: two sites per dword at a time)
     float mr[V], mu[V], mv[V], mw[V];
-    Range16 rng;  // kS16: extremes of the biased codes
+    Range16 rng;  // kS16: range test of the codes
     if constexpr (K::kBytes == 4) {
         float fxs[V];
         if constexpr (kFField) {
@@ -1127,6 +1133,7 @@ __device__ __forceinline__ void tile_update(const StepArgs &a, const char *src, 
             collide(g1, cp, mr[2 * j + 1], mu[2 * j + 1], mv[2 * j + 1], mw[2 * j + 1]);
 #pragma unroll
             for (int i = 0; i < kQ; ++i) d[i].w[j] = enc2_at<C>(g0[i], g1[i], a.sc, i, rng);
+            if constexpr (C == kS16) __builtin_amdgcn_sched_barrier(0);
         }
     }
 
@@ -1162,7 +1169,7 @@ __device__ __forceinline__ void tile_update(const StepArgs &a, const char *src, 
         // totals of the values as stored (after rounding), fluid sites only
         add_lane_totals<C, NW>(d, acc, a.sc);
     }
-    if constexpr (C == kS16) s16_flag(a, rng, mr);
+    if constexpr (C == kS16) s16_flag(a, rng);
 }
 
 // kS16 steps start here: a step whose predecessor was flagged (overflowed,
@@ -1173,7 +1180,9 @@ __device__ __forceinline__ bool s16_skip(const StepArgs &a)
 {
     if constexpr (C == kS16) {
         if (__hip_atomic_load(&a.ovf[a.par ^ 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
-            if (threadIdx.x == 0)
+            // the first workgroups mark the skip; the rest find it marked
+            if (threadIdx.x == 0 &&
+                !(__hip_atomic_load(&a.ovf[a.par], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kS16Skipped))
                 __hip_atomic_fetch_or(&a.ovf[a.par], kS16Skipped, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             return true;
         }

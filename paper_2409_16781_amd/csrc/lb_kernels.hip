@@ -72,8 +72,8 @@ __global__ __launch_bounds__(kBlock) void reduce_totals(TotalsArgs a)
     }
 }
 
-// One step of one lattice: one workgroup per tile (or a capped grid looping
-// over tiles); each workgroup stores the FP64 totals of its tiles.  In a run
+// One step of one lattice: one workgroup per tile (the grid is the tile
+// count); each workgroup stores the FP64 totals of its tile.  In a run
 // of steps, workgroup 0 also appends the previous step's totals to the ring
 // (a.prev), so a run needs one totals kernel at its end instead of one per
 // step.
@@ -86,8 +86,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(vec_wave
     char *dst = reinterpret_cast<char *>(a.dst);
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     const int ntiles = (a.nslots + kBlock - 1) / kBlock;
-    for (int b = blockIdx.x; b < ntiles; b += gridDim.x)
-        tile_update<C, NW, kSolids, kMacros, false, kFField>(a, src, dst, tile_of(b, ntiles, a.tile_order), acc, lds);
+    if ((int)blockIdx.x < ntiles)
+        tile_update<C, NW, kSolids, kMacros, false, kFField>(a, src, dst, tile_of(blockIdx.x, ntiles, a.tile_order), acc,
+                                                             lds);
     store_block_totals(acc, a.partials + 4 * (size_t)blockIdx.x);
     if (a.prev.partials != nullptr && blockIdx.x == 0) append_step_totals(a.prev);
 }
@@ -106,8 +107,7 @@ __global__ __launch_bounds__(kBlock) void step_site(StepArgs a)
     char *dst = reinterpret_cast<char *>(a.dst);
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     const int ntiles = (a.nslots + kBlock - 1) / kBlock;
-    Range16 rng;  // kS16: extremes of the biased codes
-    float rho_bad = 0.0f;
+    Range16 rng;  // kS16: range test of the codes
 
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int slot = tile * kBlock + (int)threadIdx.x;
@@ -141,7 +141,6 @@ __global__ __launch_bounds__(kBlock) void step_site(StepArgs a)
         }
         float rho, ux, uy, uz;
         collide(g, cp, rho, ux, uy, uz);
-        if (!(fabsf(rho) < 1e30f)) rho_bad = rho;
         double tot[kQ];
 #pragma unroll
         for (int i = 0; i < kQ; ++i) {
@@ -163,10 +162,7 @@ __global__ __launch_bounds__(kBlock) void step_site(StepArgs a)
         acc[2] += py;
         acc[3] += pz;
     }
-    if constexpr (C == kS16) {
-        const float rb[1] = {rho_bad};
-        s16_flag<1>(a, rng, rb);
-    }
+    if constexpr (C == kS16) s16_flag(a, rng);
     store_block_totals(acc, a.partials + 4 * (size_t)blockIdx.x);
 }
 

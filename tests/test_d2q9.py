@@ -76,29 +76,6 @@ def test_cavity_matches_oracle(nx, ny):
     lat.close()
 
 
-@pytest.mark.parametrize("grid", [1, 5, 66])
-def test_fewer_workgroups_than_tiles(grid, monkeypatch):
-    """Workgroups looping over several tiles (and group sizes of the in-launch
-    totals reduction that do not divide the grid) give the same state bit for
-    bit, and the same totals up to the order of the FP64 sums."""
-    flags = inputs.cavity_flags(1000, 70)    # 69 tiles of 256 lanes
-    outs = []
-    for g in (None, grid):
-        if g is None:
-            monkeypatch.delenv("LB_GRID2D", raising=False)
-        else:
-            monkeypatch.setenv("LB_GRID2D", str(g))
-        lat = lbm.Lattice2D(1000, 70, 0.6, flags=flags, lid=(0.1, 0.0))
-        lat.init_eq()
-        say(f"[gpu] d2q9 cavity 1000x70, grid {g}")
-        lat.step(30)
-        outs.append((lat.get_f(), lat.sums(30)))
-        lat.close()
-    m = flags == 0
-    assert np.array_equal(outs[0][0][:, m], outs[1][0][:, m])
-    assert np.allclose(outs[0][1], outs[1][1], rtol=0, atol=1e-12 * m.sum())
-
-
 def test_totals_are_reproducible():
     flags = inputs.cavity_flags(512, 300)
     got = []
