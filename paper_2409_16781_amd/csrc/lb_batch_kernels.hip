@@ -35,33 +35,20 @@ __device__ __forceinline__ void append_batch_totals(const BatchTotalsArgs &t)
 }
 
 template <int C, int NW>
-__device__ __forceinline__ void batch_tile(const BatchArgs &a, int b, EdgeLds &lds)
-{
-    const int t = tile_of(b, a.ntiles, a.tile_order);
-    const int dom = ((ConstInt *)a.tile_dom)[t];
-    ConstDomDesc &D = ((ConstDomDesc *)a.doms)[dom];
-    const StepArgs s = D.s;
-    const char *src = reinterpret_cast<const char *>(D.buf[a.parity]);
-    char *dst = reinterpret_cast<char *>(D.buf[a.parity ^ 1]);
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    tile_update<C, NW, true, false, true>(s, src, dst, t - D.tile_begin, acc, lds);
-    store_block_totals(acc, a.partials + 4 * (size_t)t);
-}
-
-// kOne: the grid has one workgroup per tile (nothing is carried from tile to
-// tile, so the register budget is one tile's); else workgroups loop over
-// tiles.
-template <int C, int NW, bool kOne>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(vec_waves<C, NW>()))) void step_batch(BatchArgs a)
 {
     __shared__ EdgeLds lds;
-    if constexpr (kOne) {
-        if ((int)blockIdx.x < a.ntiles) batch_tile<C, NW>(a, blockIdx.x, lds);
-    } else {
-        for (int b = blockIdx.x; b < a.ntiles; b += gridDim.x) {
-            batch_tile<C, NW>(a, b, lds);
-            __syncthreads();  // the totals' LDS is reused by the next tile
-        }
+    for (int b = blockIdx.x; b < a.ntiles; b += gridDim.x) {
+        const int t = tile_of(b, a.ntiles, a.tile_order);
+        const int dom = ((ConstInt *)a.tile_dom)[t];
+        ConstDomDesc &D = ((ConstDomDesc *)a.doms)[dom];
+        const StepArgs s = D.s;
+        const char *src = reinterpret_cast<const char *>(D.buf[a.parity]);
+        char *dst = reinterpret_cast<char *>(D.buf[a.parity ^ 1]);
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        tile_update<C, NW, true, false, true>(s, src, dst, t - D.tile_begin, acc, lds);
+        store_block_totals(acc, a.partials + 4 * (size_t)t);
+        __syncthreads();  // the totals' LDS is reused by the next tile
     }
     if (a.prev.partials != nullptr && blockIdx.x == 0) append_batch_totals(a.prev);
 }
@@ -96,20 +83,20 @@ __global__ __launch_bounds__(kBlock) void reduce_domains(BatchTotalsArgs a)
 }  // namespace
 
 namespace {
-template <int C, bool kOne>
+template <int C>
 void *batch_fn(int variant)
 {
-    if (variant == 1) return reinterpret_cast<void *>(&step_batch<C, 4, kOne>);
-    if (variant == 2) return reinterpret_cast<void *>(&step_batch<C, 2, kOne>);
-    return reinterpret_cast<void *>(&step_batch<C, 1, kOne>);
+    if (variant == 1) return reinterpret_cast<void *>(&step_batch<C, 4>);
+    if (variant == 2) return reinterpret_cast<void *>(&step_batch<C, 2>);
+    return reinterpret_cast<void *>(&step_batch<C, 1>);
 }
 
-void *pick_batch(int codec, int variant, bool one)
+void *pick_batch(int codec, int variant)
 {
     switch (codec) {
-        case kF32: return one ? batch_fn<kF32, true>(variant) : batch_fn<kF32, false>(variant);
-        case kF16: return one ? batch_fn<kF16, true>(variant) : batch_fn<kF16, false>(variant);
-        default: return one ? batch_fn<kBF16, true>(variant) : batch_fn<kBF16, false>(variant);
+        case kF32: return batch_fn<kF32>(variant);
+        case kF16: return batch_fn<kF16>(variant);
+        default: return batch_fn<kBF16>(variant);
     }
 }
 }  // namespace
@@ -118,7 +105,7 @@ hipError_t launch_batch_step(int codec, int variant, const BatchArgs &a, int gri
 {
     BatchArgs arg = a;
     void *params[] = {&arg};
-    return hipLaunchKernel(pick_batch(codec, variant, grid >= a.ntiles), dim3(grid), dim3(kBlock), params, 0, s);
+    return hipLaunchKernel(pick_batch(codec, variant), dim3(grid), dim3(kBlock), params, 0, s);
 }
 
 hipError_t launch_batch_totals(const BatchTotalsArgs &a, hipStream_t s)
@@ -130,8 +117,7 @@ hipError_t launch_batch_totals(const BatchTotalsArgs &a, hipStream_t s)
 int batch_occupancy(int codec, int variant)
 {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pick_batch(codec, variant, false), kBlock, 0) != hipSuccess)
-        return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pick_batch(codec, variant), kBlock, 0) != hipSuccess) return 1;
     return nb < 1 ? 1 : nb;
 }
 
