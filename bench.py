@@ -193,7 +193,7 @@ def run_batch(torch, lbm, steps, reps):
                 kernel_ms=round(kernel_ms, 5), achieved_gbs_fluid=round(gbs, 1),
                 frac_hbm=round(gbs / HBM_PEAK_GBS, 4), bytes_per_fluid_site=152,
                 shape={k: info[k] for k in ("variant", "sites_per_lane", "grid", "tiles", "tile_order", "seg_bytes",
-                                             "grid_mult", "autotuned")},
+                                             "grid_mult", "autotuned", "wg_cap")},
                 finite_totals=bool(np.all(np.isfinite(sums))))
 
 

@@ -360,7 +360,8 @@ typedef struct lb_batch lb_batch;
  * NULL is the default stream).  autotune: 0 = the default launch
  * shape (16-byte vectors of population rows, storage blocks of 32 KiB per
  * population, one workgroup per tile); 1 = time every candidate shape (sites
- * per lane, storage block size, grid size, tile order) on this batch once
+ * per lane, storage block size, grid size, tile order, and for 4-byte vectors
+ * a cap of 4 or 5 resident workgroups per compute unit) on this batch once
  * and keep the fastest (results are remembered for the rest of the process,
  * keyed by the codec and the domains' extents).  Every domain starts at rest
  * with zero force; every step counter is 0.  All device memory is allocated
@@ -412,7 +413,8 @@ long long lb_batch_steps_done(lb_batch *b);
  * domains, 6 = sites of all domains, 7 = fluid sites of all domains, 8 =
  * bytes of both population arrays of all domains, 9 = target bytes of one
  * population in a storage block, 10 = grid multiple (0: one workgroup per
- * tile), 11 = 1 if the shape was chosen by the autotuner.  -1 on error.
+ * tile), 11 = 1 if the shape was chosen by the autotuner, 12 = cap on the
+ * resident step workgroups per compute unit (0: none).  -1 on error.
  */
 long long lb_batch_query(lb_batch *b, int key);
 

@@ -602,7 +602,7 @@ class Batch:
     @property
     def info(self) -> dict:
         keys = ["variant", "sites_per_lane", "grid", "tiles", "tile_order", "domains", "sites", "fluid_sites",
-                "array_bytes", "seg_bytes", "grid_mult", "autotuned"]
+                "array_bytes", "seg_bytes", "grid_mult", "autotuned", "wg_cap"]
         return {k: self.query(i) for i, k in enumerate(keys)}
 
     def time_steps(self, n: int) -> float:

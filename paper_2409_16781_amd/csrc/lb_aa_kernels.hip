@@ -20,44 +20,24 @@ namespace {
 // hold whole rows (lds_edges).  Solid sites push nothing: their slots are the
 // targets of their neighbours' bounce-back.
 
-// Collide the V sites of a lane (FP32 arithmetic, storage codec C); rho and
-// u are not kept.
+// Collide the V sites of a lane (FP32 arithmetic, storage codec C) exactly as
+// the two-array step does; rho and u are not kept.
 template <int C, int NW>
 __device__ __forceinline__ void collide_lane(Lane<NW> (&d)[kQ], const Coll &cp)
 {
-    using K = Codec<C>;
-    float r, ux, uy, uz;
-    if constexpr (K::kBytes == 4) {
-#pragma unroll
-        for (int e = 0; e < NW; ++e) {
-            float gg[kQ];
-#pragma unroll
-            for (int i = 0; i < kQ; ++i) gg[i] = K::dec(d[i].w[e]);
-            collide(gg, cp, r, ux, uy, uz);
-#pragma unroll
-            for (int i = 0; i < kQ; ++i) d[i].w[e] = K::enc(gg[i]);
-        }
-    } else {
-#pragma unroll
-        for (int j = 0; j < NW; ++j) {
-            float g0[kQ], g1[kQ];
-#pragma unroll
-            for (int i = 0; i < kQ; ++i) K::dec2(d[i].w[j], g0[i], g1[i]);
-            collide(g0, cp, r, ux, uy, uz);
-            collide(g1, cp, r, ux, uy, uz);
-#pragma unroll
-            for (int i = 0; i < kQ; ++i) d[i].w[j] = K::enc2(g0[i], g1[i]);
-        }
-    }
+    constexpr int V = NW * 4 / Codec<C>::kBytes;
+    float mr[V], mu[V], mv[V], mw[V], fxs[V];
+    Range16 rng;
+    const Scale16 sc{};
+    collide_sites<C, NW, false>(d, cp, sc, rng, fxs, mr, mu, mv, mw);
 }
 
-// Wave budget of the in-place kernels: that of the two-array step for 4- and
-// 8-byte vectors, none for 16-byte vectors (their collision keeps pairs of
-// sites, which fits only at one wave per SIMD without spills).
+// Wave budget of the in-place kernels: that of the two-array step (the same
+// collision code).
 template <int C, int NW>
 constexpr int aa_waves()
 {
-    return NW <= 2 ? vec_waves<C, NW>() : 1;
+    return vec_waves<C, NW>();
 }
 
 // The lane's solid sites (bit e: site e is solid) and their neighbour masks.
@@ -107,7 +87,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(aa_waves
                 const StoreBase sb = store_base(F, g.own, K::kBytes);
                 if (dead == 0) {
 #pragma unroll
-                    for (int i = 0; i < kQ; ++i) stv_at<NW>(F, sb, g.own + OPP[i] * a.lay.seg, K::kBytes, d[i]);
+                    for (int i = 0; i < kQ; ++i) stv_pop<NW>(sb, (uint32_t)OPP[i] * a.lay.seg * (uint32_t)K::kBytes, d[i]);
                 } else {
 #pragma unroll
                     for (int i = 0; i < kQ; ++i)

@@ -120,7 +120,7 @@ __global__ __launch_bounds__(kBlock) void adjoint_vec(AdjArgs a)
             if (dead != (1u << V) - 1u) {
                 const StoreBase sb = store_base(nu_out, g.own, K::kBytes);
 #pragma unroll
-                for (int i = 0; i < kQ; ++i) stv_at<NW>(nu_out, sb, g.own + i * sa.lay.seg, K::kBytes, d[i]);
+                for (int i = 0; i < kQ; ++i) stv_pop<NW>(sb, (uint32_t)i * sa.lay.seg * (uint32_t)K::kBytes, d[i]);
                 float gr[V];
                 load_masks<V>(reinterpret_cast<const uint32_t *>(a.grad) + g.s0, reinterpret_cast<uint32_t(&)[V]>(gr));
 #pragma unroll

@@ -40,12 +40,16 @@ constexpr int kBatchGraphMax = 1024;
 // Launch shape of a batch.  variant: 1 / 2 / 3 = 16- / 8- / 4-byte vectors
 // per lane and population; seg_bytes: target bytes of one population's rows
 // in a storage block; grid_mult: 0 = one workgroup per tile, k > 0 = k x
-// (resident workgroups per CU) x CUs workgroups looping over the tiles.
+// (resident workgroups per CU) x CUs workgroups looping over the tiles;
+// wg_cap: at most this many resident workgroups per CU (held by dynamic LDS;
+// 0 = as many as the registers allow).  The 4-byte kernel fits six or more
+// waves per SIMD, and the best step time has been measured at four or five.
 struct Shape {
     int variant = 1;
     int seg_bytes = 32768;
     int grid_mult = 0;
     int tile_order = 0;
+    int wg_cap = 0;
 };
 
 struct Domain {
@@ -85,6 +89,7 @@ struct lb_batch {
     double *ring = nullptr;
     unsigned long long *counter = nullptr;
     int ntiles = 0, grid = 0, cus = 0;
+    size_t lds_pad = 0;  // dynamic LDS per workgroup of the step launch (the shape's wg_cap)
     int cur = 0;
     long long steps = 0;
     hipStream_t stream = nullptr;  // borrowed (NULL: the default stream)
@@ -201,8 +206,9 @@ int configure(lb_batch *b, const Shape &s)
         d.lay.nx = (uint32_t)d.nx;
         d.lay.pitch = pitch;
         d.lay.lg_r = lg;
-        d.lay.seg = R * pitch;
-        d.lay.blk = (uint64_t)kQ * d.lay.seg;
+        if (!block_fits(R * pitch, kQ, es)) return fail(LB_EINVAL, "domain %d: rows of %u elements are too long", k, pitch);
+        d.lay.seg = (uint32_t)(R * pitch);
+        d.lay.blk = (uint32_t)(kQ * R * pitch);
         d.arr_elems = (rows + R - 1) / R * d.lay.blk;
         const uint64_t slots = rows * pitch / V;
         if (slots > 0x7fffffffull) return fail(LB_EINVAL, "domain %d is too large for a batch", k);
@@ -252,7 +258,8 @@ int configure(lb_batch *b, const Shape &s)
     HIP_OR_FAIL(hipStreamSynchronize(b->stream));
     HIP_OR_FAIL(hipMemcpy(b->d_tile_dom, tile_dom.data(), tile_dom.size() * sizeof(int), hipMemcpyHostToDevice));
     if (int rc = upload_table(b)) return rc;
-    const int occ = batch_occupancy(b->codec, s.variant);
+    b->lds_pad = batch_cap_lds(b->codec, s.variant, s.wg_cap);
+    const int occ = batch_occupancy(b->codec, s.variant, b->lds_pad);
     int64_t grid = tiles;
     if (s.grid_mult > 0) grid = std::min<int64_t>(grid, (int64_t)s.grid_mult * occ * b->cus);
     b->grid = (int)std::max<int64_t>(grid, 1);
@@ -288,7 +295,7 @@ int enqueue_run(lb_batch *b, int parity, int count, hipStream_t s)
         a.tile_order = b->shape.tile_order;
         a.partials = b->partials + (size_t)(k & 1) * 4 * b->ntiles;
         if (k > 0) a.prev = batch_totals_args(b, (k - 1) & 1);
-        HIP_OR_FAIL(launch_batch_step(b->codec, b->shape.variant, a, b->grid, s));
+        HIP_OR_FAIL(launch_batch_step(b->codec, b->shape.variant, a, b->grid, b->lds_pad, s));
     }
     HIP_OR_FAIL(launch_batch_totals(batch_totals_args(b, (count - 1) & 1), s));
     return LB_OK;
@@ -409,10 +416,15 @@ int autotune(lb_batch *b)
             s.seg_bytes = seg;
             if (int rc = configure(b, s)) return rc;
             for (int gm : grid_opts) {
+                // workgroup caps: for the 4-byte kernel with one workgroup per tile
+                const int ncaps = (variant == 3 && gm == 0) ? 3 : 1;
+                for (int ci = 0; ci < ncaps; ++ci) {
                 for (int order = 0; order < 2; ++order) {
                     s.grid_mult = gm;
                     s.tile_order = order;
-                    const int occ = batch_occupancy(b->codec, variant);
+                    s.wg_cap = ci == 0 ? 0 : 3 + ci;  // none, 4, 5
+                    b->lds_pad = batch_cap_lds(b->codec, variant, s.wg_cap);
+                    const int occ = batch_occupancy(b->codec, variant, b->lds_pad);
                     int64_t grid = b->ntiles;
                     if (gm > 0) grid = std::min<int64_t>(grid, (int64_t)gm * occ * b->cus);
                     b->grid = (int)std::max<int64_t>(grid, 1);
@@ -428,6 +440,7 @@ int autotune(lb_batch *b)
                         best_ms = ms;
                         best = s;
                     }
+                }
                 }
             }
         }
@@ -540,7 +553,8 @@ lb_batch *lb_batch_create(int count, const int *dims, const double *taus, const 
     s.seg_bytes = (int)env_long("LB_BATCH_SEG_BYTES", 32768);
     s.grid_mult = (int)env_long("LB_BATCH_GRID", 0);
     s.tile_order = (int)env_long("LB_BATCH_TILE_ORDER", 0);
-    if (s.variant < 1 || s.variant > 3 || s.seg_bytes < 64 || s.grid_mult < 0) {
+    s.wg_cap = (int)env_long("LB_BATCH_WG_CAP", 0);
+    if (s.variant < 1 || s.variant > 3 || s.seg_bytes < 64 || s.grid_mult < 0 || s.wg_cap < 0 || (s.wg_cap > 0 && s.wg_cap < 3)) {
         release_all(b);
         delete b;
         fail(LB_EINVAL, "invalid LB_BATCH_* setting");
@@ -722,6 +736,7 @@ long long lb_batch_query(lb_batch *b, int key)
         case 9: return b->shape.seg_bytes;
         case 10: return b->shape.grid_mult;
         case 11: return b->tuned ? 1 : 0;
+        case 12: return b->shape.wg_cap;
         default: fail(LB_EINVAL, "unknown query key %d", key); return -1;
     }
 }
@@ -749,7 +764,7 @@ int lb_batch_time_step_kernel(lb_batch *b, int n, double *ms)
         a.tile_order = b->shape.tile_order;
         a.partials = b->partials;
         if (hipEventRecord(ev[2 * k], b->stream) != hipSuccess) rc = fail(LB_EHIP, "hipEventRecord");
-        if (rc == LB_OK && launch_batch_step(b->codec, b->shape.variant, a, b->grid, b->stream) != hipSuccess)
+        if (rc == LB_OK && launch_batch_step(b->codec, b->shape.variant, a, b->grid, b->lds_pad, b->stream) != hipSuccess)
             rc = fail(LB_EHIP, "batch step launch");
         if (rc == LB_OK && hipEventRecord(ev[2 * k + 1], b->stream) != hipSuccess) rc = fail(LB_EHIP, "hipEventRecord");
         if (rc == LB_OK) {

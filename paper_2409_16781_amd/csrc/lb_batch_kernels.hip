@@ -101,11 +101,24 @@ void *pick_batch(int codec, int variant)
 }
 }  // namespace
 
-hipError_t launch_batch_step(int codec, int variant, const BatchArgs &a, int grid, hipStream_t s)
+hipError_t launch_batch_step(int codec, int variant, const BatchArgs &a, int grid, size_t lds_pad, hipStream_t s)
 {
     BatchArgs arg = a;
     void *params[] = {&arg};
-    return hipLaunchKernel(pick_batch(codec, variant), dim3(grid), dim3(kBlock), params, 0, s);
+    return hipLaunchKernel(pick_batch(codec, variant), dim3(grid), dim3(kBlock), params, lds_pad, s);
+}
+
+size_t batch_cap_lds(int codec, int variant, int wg_cap)
+{
+    if (wg_cap <= 0) return 0;
+    hipFuncAttributes at;
+    int dev = 0, lds_cu = 0;
+    if (hipFuncGetAttributes(&at, pick_batch(codec, variant)) != hipSuccess || hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess)
+        return 0;
+    // wg_cap + 1 workgroups of (static + pad) bytes must not fit in a CU's LDS
+    const size_t per = (size_t)lds_cu / (size_t)(wg_cap + 1) + 1;
+    return per > at.sharedSizeBytes ? per - at.sharedSizeBytes : 0;
 }
 
 hipError_t launch_batch_totals(const BatchTotalsArgs &a, hipStream_t s)
@@ -114,10 +127,11 @@ hipError_t launch_batch_totals(const BatchTotalsArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
-int batch_occupancy(int codec, int variant)
+int batch_occupancy(int codec, int variant, size_t lds_pad)
 {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pick_batch(codec, variant), kBlock, 0) != hipSuccess) return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pick_batch(codec, variant), kBlock, lds_pad) != hipSuccess)
+        return 1;
     return nb < 1 ? 1 : nb;
 }
 

@@ -566,8 +566,14 @@ int create_impl(lb_lattice **out, int nx, int ny, int nz, double tau, const uint
         delete h;
         return fail(LB_EINVAL, "LB_SEG_PAD must be a non-negative multiple of 128");
     }
-    h->lay.seg = (uint64_t)rows * nx + (uint64_t)seg_pad;
-    h->lay.blk = (uint64_t)kQ * h->lay.seg;
+    const uint64_t seg = (uint64_t)rows * nx + (uint64_t)seg_pad;
+    if (!block_fits(seg, kQ, h->esize)) {
+        delete h;
+        return fail(LB_EINVAL, "a storage block of %llu elements per population (rows of %d sites) reaches 1 GiB",
+                    (unsigned long long)seg, nx);
+    }
+    h->lay.seg = (uint32_t)seg;
+    h->lay.blk = (uint32_t)(kQ * seg);
     const uint64_t nblocks = (nrows + rows - 1) / rows;
     h->arr_elems = nblocks * h->lay.blk;
 

@@ -184,7 +184,12 @@ lb2d_lattice *lb2d_create(int nx, int ny, double tau, const uint8_t *flags, doub
     while ((1ull << lg) < R) ++lg;
     h->lay.nx = h->lay.pitch = (uint32_t)nx;
     h->lay.lg_r = lg;
-    h->lay.seg = R * nx;
+    if (!block_fits((uint64_t)R * nx, 9, 4)) {
+        delete h;
+        fail(LB_EINVAL, "rows of %d sites are too long", nx);
+        return nullptr;
+    }
+    h->lay.seg = (uint32_t)(R * nx);
     h->lay.blk = 9 * h->lay.seg;
     h->arr_elems = ((uint64_t)ny + R - 1) / R * h->lay.blk;
     const uint64_t tiles = (n / h->vsites + kBlock - 1) / kBlock;

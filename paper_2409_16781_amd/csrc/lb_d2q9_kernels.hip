@@ -182,7 +182,7 @@ __global__ __launch_bounds__(kBlock) void step2d(Step2Args a)
             if (dead != (1u << V) - 1u) {
                 const StoreBase sb = store_base(dst, own, 4);
 #pragma unroll
-                for (int i = 0; i < kQ2; ++i) stv_at<NW>(dst, sb, own + i * a.lay.seg, 4, d[i]);
+                for (int i = 0; i < kQ2; ++i) stv_pop<NW>(sb, (uint32_t)i * a.lay.seg * 4u, d[i]);
             }
             // totals of the stored values (dead sites hold zero), in FP64
             double t[kQ2];

@@ -135,6 +135,8 @@ constexpr int kStoreAux = 2 | 16;  // nt | sc1
 struct StoreBase {
     __amdgpu_buffer_rsrc_t rsrc;
     uint64_t first;  // element offset of the descriptor's base
+    uint32_t lane;   // byte offset of the lane's own element from that base
+    char *own;       // the lane's own element (stores without the descriptor)
 };
 
 template <int NW>
@@ -166,10 +168,39 @@ __device__ __forceinline__ StoreBase store_base(char *dst, uint64_t own, int byt
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)own);
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(own >> 32));
     sb.first = ((uint64_t)hi << 32) | lo;
+    sb.lane = (uint32_t)(own - sb.first) * (uint32_t)bytes;
 #if LB_STORE_SC1
     sb.rsrc = __builtin_amdgcn_make_buffer_rsrc(dst + sb.first * (uint64_t)bytes, 0, 0x7fffffff, 0x00020000);
+    sb.own = nullptr;
+#else
+    sb.own = dst + own * (uint64_t)bytes;
 #endif
     return sb;
+}
+
+// Store of a lane vector at byte offset off (wave-uniform: the population's
+// segment in the block) from the lane's own element.  A block holds fewer
+// than 2^30 bytes and a wave's sites lie in at most two blocks unless the
+// blocks are tiny, so lane + off stays below 2^31.
+template <int NW>
+__device__ __forceinline__ void stv_pop(const StoreBase &sb, uint32_t off, const Lane<NW> &d)
+{
+#if LB_STORE_SC1
+    const int o = (int)(sb.lane + off);
+    if constexpr (NW == 4) {
+        typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+        v4u v = {d.w[0], d.w[1], d.w[2], d.w[3]};
+        __builtin_amdgcn_raw_buffer_store_b128(v, sb.rsrc, o, 0, kStoreAux);
+    } else if constexpr (NW == 2) {
+        typedef unsigned int v2u __attribute__((ext_vector_type(2)));
+        v2u v = {d.w[0], d.w[1]};
+        __builtin_amdgcn_raw_buffer_store_b64(v, sb.rsrc, o, 0, kStoreAux);
+    } else {
+        __builtin_amdgcn_raw_buffer_store_b32(d.w[0], sb.rsrc, o, 0, kStoreAux);
+    }
+#else
+    stv<NW>(sb.own + off, d);
+#endif
 }
 
 __device__ __forceinline__ uint32_t fastdiv(uint32_t n, const FastDiv &f)
@@ -911,12 +942,26 @@ __device__ __forceinline__ uint32_t gather(const StepArgs &a, const char *src, c
     // +-1 shifts along x (all lanes take part in the DPP moves).  The element
     // a lane needs from beyond its wave or across the periodic wrap comes
     // through LDS when the tile holds whole rows (each element is then read
-    // from HBM once), else by a direct load.  The lane holding site nx - 1
-    // is the row's right edge (with padded rows that site need not be the
-    // last of the vector).
+    // from HBM once), else by a direct load, issued here behind the pulls so
+    // that the wave waits for one round trip, not two.  The lane holding site
+    // nx - 1 is the row's right edge (with padded rows that site need not be
+    // the last of the vector).
     const bool left_edge = (lane == 0) || (x0 == 0);
     const bool row_end = x0 + V >= nx;
     const bool right_edge = (lane == 63) || row_end;
+    const uint32_t xl = (x0 == 0 ? nx : x0) - 1;
+    const uint32_t xr = row_end ? 0 : x0 + V;
+    uint32_t eprev[5], enext[5];
+    if (!a.lds_edges) {
+        if (left_edge) {
+#pragma unroll
+            for (int k = 0; k < 5; ++k) eprev[k] = ld_elem<C>(src, rb[kPlusX[k]] + xl);
+        }
+        if (right_edge) {
+#pragma unroll
+            for (int k = 0; k < 5; ++k) enext[k] = ld_elem<C>(src, rb[kMinusX[k]] + xr);
+        }
+    }
     const int wave = threadIdx.x >> 6;
     const int rit = (int)threadIdx.x >> a.lg_row_lanes;  // row within the tile
     if (a.lds_edges) {
@@ -939,8 +984,6 @@ __device__ __forceinline__ uint32_t gather(const StepArgs &a, const char *src, c
         }
         __syncthreads();
     }
-    const uint32_t xl = (x0 == 0 ? nx : x0) - 1;
-    const uint32_t xr = row_end ? 0 : x0 + V;
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
         const int i = kPlusX[k];  // c_x = +1: pull from x - 1
@@ -949,7 +992,7 @@ __device__ __forceinline__ uint32_t gather(const StepArgs &a, const char *src, c
             if (a.lds_edges) {
                 prev = x0 == 0 ? lds.row_last[rit][k] : lds.wave_last[wave - 1][k];
             } else {
-                prev = ld_elem<C>(src, rb[i] + xl);
+                prev = eprev[k];
                 if constexpr (K::kBytes == 2) prev <<= 16;  // as the upper half of a dword
             }
         }
@@ -964,7 +1007,7 @@ __device__ __forceinline__ uint32_t gather(const StepArgs &a, const char *src, c
             if (a.lds_edges)
                 next = row_end ? lds.row_first[rit][k] : lds.wave_first[wave + 1][k];
             else
-                next = ld_elem<C>(src, rb[i] + xr);
+                next = enext[k];
         }
         if constexpr (K::kBytes == 2) next &= 0xffffu;
         d[i] = shift_in_from_right<C, NW>(d[i], next);
@@ -1036,6 +1079,76 @@ __device__ __forceinline__ Coll coll_at(const Coll &p, float fx)
     return q;
 }
 
+// Collide the V sites of a lane in place (loaded vectors in, values to store
+// out), with their moments in mr/mu/mv/mw.  kFField: site e's x-force is the
+// uniform one plus fxs[e] (FP32 storage).  Every kernel that collides a lane
+// goes through here, so equal inputs give equal bits whichever kernel runs.
+template <int C, int NW, bool kFField>
+__device__ __forceinline__ void collide_sites(Lane<NW> (&d)[kQ], const Coll &cp, const Scale16 &sc, Range16 &rng,
+                                              const float (&fxs)[NW * 4 / Codec<C>::kBytes],
+                                              float (&mr)[NW * 4 / Codec<C>::kBytes],
+                                              float (&mu)[NW * 4 / Codec<C>::kBytes],
+                                              float (&mv)[NW * 4 / Codec<C>::kBytes],
+                                              float (&mw)[NW * 4 / Codec<C>::kBytes])
+{
+    using K = Codec<C>;
+    constexpr int V = NW * 4 / K::kBytes;
+    static_assert(!kFField || K::kBytes == 4, "force fields: FP32 storage");
+    if constexpr (K::kBytes == 4) {
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            float gg[kQ];
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) gg[i] = K::dec(d[i].w[e]);
+            if constexpr (kFField) {
+                const Coll q = coll_at(cp, cp.fx + fxs[e]);
+                collide(gg, q, mr[e], mu[e], mv[e], mw[e]);
+            } else {
+                collide(gg, cp, mr[e], mu[e], mv[e], mw[e]);
+            }
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) d[i].w[e] = K::enc(gg[i]);
+        }
+    } else if constexpr (NW >= 4) {
+        // 16-byte vectors of 16-bit values (8 sites per lane): one site at a
+        // time, its results written back into its half of each dword, so
+        // the registers hold the loaded vectors plus one site.
+#pragma unroll
+        for (int j = 0; j < NW; ++j) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                float gg[kQ];
+#pragma unroll
+                for (int i = 0; i < kQ; ++i) gg[i] = dec_at<C>(h ? d[i].w[j] >> 16 : d[i].w[j] & 0xffffu, sc, i);
+                collide(gg, cp, mr[2 * j + h], mu[2 * j + h], mv[2 * j + h], mw[2 * j + h]);
+#pragma unroll
+                for (int i = 0; i < kQ; ++i) {
+                    const uint32_t b = enc_at<C>(gg[i], sc, i, rng);
+                    d[i].w[j] = h ? ((d[i].w[j] & 0xffffu) | (b << 16)) : ((d[i].w[j] & 0xffff0000u) | b);
+                }
+                // the packed words as they now stand: the next site decodes
+                // from these registers, so no two sites' values are live at once
+#pragma unroll
+                for (int i = 0; i < kQ; ++i) {
+#pragma unroll
+                    for (int k = 0; k < NW; ++k) asm volatile("" : "+v"(d[i].w[k]));
+                }
+            }
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < NW; ++j) {
+            float g0[kQ], g1[kQ];
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) dec2_at<C>(d[i].w[j], sc, i, g0[i], g1[i]);
+            collide(g0, cp, mr[2 * j], mu[2 * j], mv[2 * j], mw[2 * j]);
+            collide(g1, cp, mr[2 * j + 1], mu[2 * j + 1], mv[2 * j + 1], mw[2 * j + 1]);
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) d[i].w[j] = enc2_at<C>(g0[i], g1[i], sc, i, rng);
+        }
+    }
+}
+
 // kS16: a lane whose codes left their class's range, or were not finite (a
 // blown-up site: the fixed point would hide a NaN), flags the step with the
 // classes to widen; the step is redone from its intact source array with
@@ -1077,65 +1190,11 @@ __device__ __forceinline__ void tile_update(const StepArgs &a, const char *src, 
     // collide site by site (16-bit codecs: two sites per dword at a time)
     float mr[V], mu[V], mv[V], mw[V];
     Range16 rng;  // kS16: range test of the codes
-    if constexpr (K::kBytes == 4) {
-        float fxs[V];
-        if constexpr (kFField) {
-            load_masks<V>(reinterpret_cast<const uint32_t *>(a.fx_field) + g.s0,
-                          reinterpret_cast<uint32_t(&)[V]>(fxs));
-        }
-#pragma unroll
-        for (int e = 0; e < V; ++e) {
-            float gg[kQ];
-#pragma unroll
-            for (int i = 0; i < kQ; ++i) gg[i] = K::dec(d[i].w[e]);
-            if constexpr (kFField) {
-                const Coll q = coll_at(cp, cp.fx + fxs[e]);
-                collide(gg, q, mr[e], mu[e], mv[e], mw[e]);
-            } else {
-                collide(gg, cp, mr[e], mu[e], mv[e], mw[e]);
-            }
-#pragma unroll
-            for (int i = 0; i < kQ; ++i) d[i].w[e] = K::enc(gg[i]);
-        }
-    } else if constexpr (NW >= 4) {
-        // 16-byte vectors of 16-bit values (8 sites per lane): one site at a
-        // time, its results written back into its half of each dword, so
-        // the registers hold the loaded vectors plus one site.
-#pragma unroll
-        for (int j = 0; j < NW; ++j) {
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                float gg[kQ];
-#pragma unroll
-                for (int i = 0; i < kQ; ++i) gg[i] = dec_at<C>(h ? d[i].w[j] >> 16 : d[i].w[j] & 0xffffu, a.sc, i);
-                collide(gg, cp, mr[2 * j + h], mu[2 * j + h], mv[2 * j + h], mw[2 * j + h]);
-#pragma unroll
-                for (int i = 0; i < kQ; ++i) {
-                    const uint32_t b = enc_at<C>(gg[i], a.sc, i, rng);
-                    d[i].w[j] = h ? ((d[i].w[j] & 0xffffu) | (b << 16)) : ((d[i].w[j] & 0xffff0000u) | b);
-                }
-                // the packed words as they now stand: the next site decodes
-                // from these registers, so no two sites' values are live at once
-#pragma unroll
-                for (int i = 0; i < kQ; ++i) {
-#pragma unroll
-                    for (int k = 0; k < NW; ++k) asm volatile("" : "+v"(d[i].w[k]));
-                }
-            }
-        }
-    } else {
-#pragma unroll
-        for (int j = 0; j < NW; ++j) {
-            float g0[kQ], g1[kQ];
-#pragma unroll
-            for (int i = 0; i < kQ; ++i) dec2_at<C>(d[i].w[j], a.sc, i, g0[i], g1[i]);
-            collide(g0, cp, mr[2 * j], mu[2 * j], mv[2 * j], mw[2 * j]);
-            collide(g1, cp, mr[2 * j + 1], mu[2 * j + 1], mv[2 * j + 1], mw[2 * j + 1]);
-#pragma unroll
-            for (int i = 0; i < kQ; ++i) d[i].w[j] = enc2_at<C>(g0[i], g1[i], a.sc, i, rng);
-            if constexpr (C == kS16) __builtin_amdgcn_sched_barrier(0);
-        }
+    float fxs[V];
+    if constexpr (kFField) {
+        load_masks<V>(reinterpret_cast<const uint32_t *>(a.fx_field) + g.s0, reinterpret_cast<uint32_t(&)[V]>(fxs));
     }
+    collide_sites<C, NW, kFField>(d, cp, a.sc, rng, fxs, mr, mu, mv, mw);
 
     if (g.active) {
         // Solid (and padding) sites hold zero in both arrays: they are
@@ -1156,8 +1215,9 @@ __device__ __forceinline__ void tile_update(const StepArgs &a, const char *src, 
         }
         if (dead != (1u << V) - 1u) {
             const StoreBase sb = store_base(dst, g.own, K::kBytes);
+            const uint32_t segb = a.lay.seg * (uint32_t)K::kBytes;
 #pragma unroll
-            for (int i = 0; i < kQ; ++i) stv_at<NW>(dst, sb, g.own + i * a.lay.seg, K::kBytes, d[i]);
+            for (int i = 0; i < kQ; ++i) stv_pop<NW>(sb, (uint32_t)i * segb, d[i]);
         }
         if constexpr (kMacros) {
             const size_t n = (size_t)a.nx * a.ny * a.nz;

@@ -50,19 +50,29 @@ inline FastDiv make_fastdiv(uint32_t d)
 // (pitch > nx only in batches, where rows are padded to whole vectors).
 // R = 1 stores the 19 populations of a row one after the other; R >= ny*nz is
 // plain structure of arrays.  Blocks of tens of KiB per population keep the
-// 38 streams of a step close together in HBM.
+// 38 streams of a step close together in HBM.  A block holds fewer than 2^30
+// bytes (checked when a layout is made), so seg and blk are 32-bit and the
+// offset of an element inside its block is a 32-bit product.
 struct Layout {
     uint32_t nx;     // sites per row
     uint32_t pitch;  // elements per stored row
     uint32_t lg_r;   // log2(rows per block)
+    uint32_t seg;    // elements of one population in one block
+    uint32_t blk;    // 19 * seg (9 * seg for D2Q9): elements of one block
     uint32_t pad_;
-    uint64_t seg;    // elements of one population in one block
-    uint64_t blk;    // 19 * seg: elements of one block
     __host__ __device__ uint64_t row_base(uint32_t r) const
     {
-        return (uint64_t)(r >> lg_r) * blk + (uint64_t)(r & ((1u << lg_r) - 1u)) * pitch;
+        return (uint64_t)(r >> lg_r) * blk + (r & ((1u << lg_r) - 1u)) * pitch;
     }
 };
+
+// Whether a block of q populations of seg elements of esize bytes stays below
+// 2^30 bytes: the store offsets from a wave's first element (inside one block,
+// or two when the wave's rows cross a block boundary) then fit in 31 bits.
+inline bool block_fits(uint64_t seg, int q, int esize)
+{
+    return seg * (uint64_t)q * (uint64_t)esize < 0x40000000ull;
+}
 
 // Per-launch constants of the collision (computed once on the host, in FP32).
 struct Coll {
@@ -253,11 +263,14 @@ long env_long(const char *name, long dflt);  // integer environment setting (tun
         if (e_ != hipSuccess) return lbm::fail(LB_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 // Batches: variant 1 / 2 / 3 as above (always with bounce-back masks).
-hipError_t launch_batch_step(int codec, int variant, const BatchArgs &a, int grid, hipStream_t s);
+// lds_pad: dynamic LDS bytes per workgroup (0, or batch_cap_lds's value to
+// hold the kernel to wg_cap resident workgroups per compute unit).
+hipError_t launch_batch_step(int codec, int variant, const BatchArgs &a, int grid, size_t lds_pad, hipStream_t s);
+size_t batch_cap_lds(int codec, int variant, int wg_cap);
 hipError_t launch_batch_totals(const BatchTotalsArgs &a, hipStream_t s);
 // One adjoint step; variant 1 / 2 / 3 = 4 / 2 / 1 sites per lane (FP32 storage).
 hipError_t launch_adjoint(int variant, bool first, const AdjArgs &a, int grid, hipStream_t s);
-int batch_occupancy(int codec, int variant);
+int batch_occupancy(int codec, int variant, size_t lds_pad);
 // Outlet flux objective: J of a stored state (one workgroup, fixed-order FP64
 // sum), its seed dJ/dS_N written into a zeroed storage-layout array, and its
 // direct term added to a gradient.
