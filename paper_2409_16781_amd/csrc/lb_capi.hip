@@ -285,6 +285,11 @@ constexpr int kS16MaxExp = 60;  // narrowest range: |g| < 2^-45
 
 int enqueue_steps(lb_lattice *h, int n, float *rho, float *u);
 
+// count steps from buf[from] as one run with chained totals.  path (count + 1
+// arrays, or NULL for the A/B pair): step k reads path[k] and writes
+// path[k + 1].
+int enqueue_run(lb_lattice *h, int from, int count, hipStream_t s, const TotalsBufs &tb, void *const *path = nullptr);
+
 // Wait for the lattice's work; if a scaled-storage step overflowed, widen
 // the range of each weight class whose codes left it by one bit
 // (re-encoding the intact source array of the first flagged step), and redo
@@ -360,9 +365,10 @@ int enqueue_one(lb_lattice *h, int from, float *rho, float *u, hipStream_t s, co
 // partials into buffer k & 1, the first workgroup of step k + 1 appends the
 // totals of step k, and one totals kernel closes the run.  The ring then
 // holds the same values as with a totals kernel after every step.
-int enqueue_run(lb_lattice *h, int from, int count, hipStream_t s, const TotalsBufs &tb)
+int enqueue_run(lb_lattice *h, int from, int count, hipStream_t s, const TotalsBufs &tb, void *const *path)
 {
     if (h->inplace || h->variant == 0) {
+        if (path) return fail(LB_EINVAL, "explicit step buffers need the two-array row kernels");
         for (int k = 0; k < count; ++k) {
             int rc = enqueue_one(h, from ^ (k & 1), nullptr, nullptr, s, tb);
             if (rc) return rc;
@@ -371,6 +377,10 @@ int enqueue_run(lb_lattice *h, int from, int count, hipStream_t s, const TotalsB
     }
     for (int k = 0; k < count; ++k) {
         StepArgs a = step_args(h, from ^ (k & 1), nullptr, nullptr);
+        if (path) {
+            a.src = path[k];
+            a.dst = path[k + 1];
+        }
         a.partials = tb.partials + (size_t)(k & 1) * 4 * h->grid;
         if (k > 0) a.prev = totals_args(h, (k - 1) & 1, tb, from ^ ((k - 1) & 1));
         HIP_OR_FAIL(launch_step(h->codec, h->variant, h->solids, false, a, h->grid, s));
@@ -904,11 +914,21 @@ int grad_impl(lb_lattice *h, int nsteps, int every, const float *seed, float *gr
         if (rc == LB_OK && e != hipSuccess) rc = fail(LB_EHIP, "%s: %s", what, hipGetErrorString(e));
     };
     // forward: a checkpoint, then the segment's ordinary steps as one run
-    // (chained totals); the lattice ends at step nsteps
+    // (chained totals); the lattice ends at step nsteps.  The last segment's
+    // intermediate states are written to the sweep's state buffers, so the
+    // backward pass need not recompute that segment.
     for (int k = 0; k < nck && rc == LB_OK; ++k) {
         const int len = std::min(every, nsteps - k * every);
         hip(hipMemcpyAsync(ck[k], h->buf[h->cur], abytes, hipMemcpyDeviceToDevice, h->stream), "checkpoint");
-        if (rc == LB_OK) rc = enqueue_run(h, h->cur, len, h->stream, own_bufs(h));
+        if (rc == LB_OK && k == nck - 1) {
+            std::vector<void *> path(len + 1);
+            path[0] = h->buf[h->cur];
+            for (int j = 1; j < len; ++j) path[j] = states[j];
+            path[len] = h->buf[h->cur ^ (len & 1)];
+            rc = enqueue_run(h, h->cur, len, h->stream, own_bufs(h), path.data());
+        } else if (rc == LB_OK) {
+            rc = enqueue_run(h, h->cur, len, h->stream, own_bufs(h));
+        }
         if (rc == LB_OK) {
             h->cur ^= len & 1;
             h->steps += len;
@@ -929,14 +949,14 @@ int grad_impl(lb_lattice *h, int nsteps, int every, const float *seed, float *gr
     if (rc == LB_OK) hip(hipMemsetAsync(grad, 0, h->n * sizeof(float), h->stream), "hipMemsetAsync");
     if (rc == LB_OK) hip(hipMemsetAsync(nu[0], 0, abytes, h->stream), "hipMemsetAsync");
     if (rc == LB_OK) hip(hipMemsetAsync(nu[1], 0, abytes, h->stream), "hipMemsetAsync");
-    // backward, segment by segment from the last; each segment is recomputed
-    // from its checkpoint (recomputed steps write no totals)
+    // backward, segment by segment from the last; each segment but the last
+    // is recomputed from its checkpoint (recomputed steps write no totals)
     int cur_nu = 0;
     bool first = true;
     for (int k = nck - 1; k >= 0 && rc == LB_OK; --k) {
         const int start = k * every, stop = std::min(start + every, nsteps);
         states[0] = ck[k];
-        for (int j = 1; j < stop - start && rc == LB_OK; ++j) {
+        for (int j = 1; j < stop - start && rc == LB_OK && k < nck - 1; ++j) {
             StepArgs a = step_args(h, 0, nullptr, nullptr);
             a.src = states[j - 1];
             a.dst = states[j];
