@@ -227,6 +227,33 @@ def test_autotuned_shape_matches_default():
     b2.close()
 
 
+@pytest.mark.parametrize("cap", [4, 5])
+def test_workgroup_cap_changes_nothing_but_occupancy(cap, monkeypatch):
+    """A cap on the resident workgroups per CU (dynamic LDS on the 4-byte
+    kernel, one of the autotuner's candidates) gives the same state and the
+    same totals, bit for bit."""
+    doms = mixed_domains()
+    monkeypatch.setenv("LB_BATCH_KERNEL", "3")
+    b1 = make_batch(doms, "f32")
+    monkeypatch.setenv("LB_BATCH_WG_CAP", str(cap))
+    b2 = make_batch(doms, "f32")
+    assert b1.info["wg_cap"] == 0 and b2.info["wg_cap"] == cap
+    say(f"  4-byte batch kernel, cap {cap} workgroups per CU")
+    b1.step(70)
+    b2.step(70)
+    for k in range(len(doms)):
+        assert np.array_equal(b1.get_f(k), b2.get_f(k)), k
+        assert np.array_equal(b1.sums(k, 70), b2.sums(k, 70)), k
+    b1.close()
+    b2.close()
+
+
+def test_invalid_workgroup_cap_is_refused(monkeypatch):
+    monkeypatch.setenv("LB_BATCH_WG_CAP", "2")
+    with pytest.raises(lbm.LBError):
+        make_batch(mixed_domains()[:1], "f32")
+
+
 def test_batch_domain_equals_single_lattice():
     """A domain advanced inside a batch matches the same lattice advanced
     alone through lb_step (same arithmetic per site)."""

@@ -355,6 +355,10 @@ def test_errors_on_device():
     require_gpu()
     with pytest.raises(lbm.LBError):
         lbm.Lattice(8, 8, 8, 0.5)
+    # rows so long that one storage block would reach 1 GiB: refused before
+    # anything is allocated (the kernels' in-block offsets are 32-bit)
+    with pytest.raises(lbm.LBError, match="storage block"):
+        lbm.Lattice(1 << 24, 1, 1, 0.8)
     lat = lbm.Lattice(8, 8, 8, 0.8)
     with pytest.raises(lbm.LBError):
         lat.sums(1)        # no steps yet
