@@ -384,15 +384,24 @@ def cpu_baseline(cfg, steps):
 
 
 def cpu_model():
-    """The host CPU's model name (from /proc/cpuinfo; None where it is absent)."""
+    """The host CPU's model name, with its family and model numbers (from
+    /proc/cpuinfo: a virtual machine may report a short name); None where it
+    is absent."""
+    fields = {}
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
+                if not line.strip():
+                    break  # the first processor's block is enough
+                key, _, val = line.partition(":")
+                fields[key.strip()] = val.strip()
     except OSError:
-        pass
-    return None
+        return None
+    name = fields.get("model name")
+    if name is None:
+        return None
+    extra = [f"{k} {fields[k]}" for k in ("cpu family", "model", "stepping") if k in fields]
+    return f"{name} ({', '.join(extra)})" if extra else name
 
 
 def main():
