@@ -218,7 +218,7 @@ int configure(lb_batch *b, const Shape &s)
         if ((int64_t)tiles + d.ntiles > 0x7fffffffll) return fail(LB_EINVAL, "too many tiles in the batch");
         tiles += d.ntiles;
         const int row_lanes = (int)(pitch / V);
-        d.lds_edges = (pitch == (uint32_t)d.nx && row_lanes <= kBlock && kBlock % row_lanes == 0) ? 1 : 0;
+        d.lds_edges = 1;  // x-edge elements held in the same tile pass through LDS
         d.lg_row_lanes = 0;
         while ((1 << d.lg_row_lanes) < row_lanes) ++d.lg_row_lanes;
         // both arrays of the domain, each starting on a 256-byte boundary

@@ -135,13 +135,12 @@ StepArgs step_args(const lb_lattice *h, int from, float *rho, float *u, int vari
     a.ny = h->ny;
     a.nz = h->nz;
     a.nslots = (int)(h->n / (uint64_t)vsites);
-    // tiles of kBlock lanes hold whole rows when the lanes per row divide kBlock
+    // lanes per row (in-place lattices hold whole rows per tile); x-edge
+    // elements pass through LDS within a tile (LB_LDS_EDGES=0: direct loads,
+    // for comparison)
     const int row_lanes = h->nx / vsites;
     a.tile_order = h->tile_order;
-    a.lds_edges = (variant != 0 && h->nx % vsites == 0 && row_lanes <= kBlock && (kBlock % row_lanes) == 0 &&
-                   (h->inplace || env_long("LB_LDS_EDGES", 1) != 0))
-                      ? 1
-                      : 0;
+    a.lds_edges = (variant != 0 && (h->inplace || env_long("LB_LDS_EDGES", 1) != 0)) ? 1 : 0;
     a.lg_row_lanes = 0;
     while ((1 << a.lg_row_lanes) < row_lanes) ++a.lg_row_lanes;
     a.div_pitch = make_fastdiv((uint32_t)h->nx);

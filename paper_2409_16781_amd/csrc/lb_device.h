@@ -855,6 +855,7 @@ struct TileGeom {
     bool active;              // the lane's slot exists (else it repeats the last slot)
     uint32_t s0;              // stored index of the first site (row * pitch + x0)
     uint32_t row, x0, y, z, ym, yp, zm, zp;
+    uint32_t row0;            // row of the tile's first slot (wave-uniform)
     uint64_t own;             // element offset of the first site, population 0
 };
 
@@ -869,6 +870,7 @@ __device__ __forceinline__ TileGeom tile_geom(const StepArgs &a, int tile)
     g.s0 = (uint32_t)(g.active ? slot : a.nslots - 1) * V;
     g.row = fastdiv(g.s0, a.div_pitch);
     g.x0 = g.s0 - g.row * pitch;
+    g.row0 = fastdiv((uint32_t)(tile * kBlock) * V, a.div_pitch);
     g.z = fastdiv(g.row, a.div_ny);
     g.y = g.row - g.z * ny;
     g.ym = (g.y == 0 ? ny : g.y) - 1;
@@ -941,34 +943,46 @@ __device__ __forceinline__ uint32_t gather(const StepArgs &a, const char *src, c
 
     // +-1 shifts along x (all lanes take part in the DPP moves).  The element
     // a lane needs from beyond its wave or across the periodic wrap comes
-    // through LDS when the tile holds whole rows (each element is then read
-    // from HBM once), else by a direct load, issued here behind the pulls so
-    // that the wave waits for one round trip, not two.  The lane holding site
-    // nx - 1 is the row's right edge (with padded rows that site need not be
-    // the last of the vector).
+    // through LDS when the lane that holds it is in the same tile (each
+    // element is then read from HBM once); only lanes whose source lies in
+    // another tile (a row crossing the tile's first or last slot, the
+    // tile's outer wave edges) load it directly, issued here behind the
+    // pulls so that the wave waits for one round trip, not two.  The lane
+    // holding site nx - 1 is the row's right edge (with padded rows that
+    // site need not be the last of the vector).
     const bool left_edge = (lane == 0) || (x0 == 0);
     const bool row_end = x0 + V >= nx;
     const bool right_edge = (lane == 63) || row_end;
     const uint32_t xl = (x0 == 0 ? nx : x0) - 1;
     const uint32_t xr = row_end ? 0 : x0 + V;
-    uint32_t eprev[5], enext[5];
-    if (!a.lds_edges) {
-        if (left_edge) {
-#pragma unroll
-            for (int k = 0; k < 5; ++k) eprev[k] = ld_elem<C>(src, rb[kPlusX[k]] + xl);
-        }
-        if (right_edge) {
-#pragma unroll
-            for (int k = 0; k < 5; ++k) enext[k] = ld_elem<C>(src, rb[kMinusX[k]] + xr);
-        }
-    }
     const int wave = threadIdx.x >> 6;
-    const int rit = (int)threadIdx.x >> a.lg_row_lanes;  // row within the tile
+    // the row's last site is (nx - 1) / V slots after its first
+    const bool prev_lds = a.lds_edges && (x0 == 0 ? (int)threadIdx.x + (int)((nx - 1) / V) < kBlock : wave > 0);
+    const bool next_lds = a.lds_edges && (row_end ? (int)threadIdx.x >= (int)(x0 / V) : wave < kBlock / 64 - 1);
+    uint32_t eprev[5], enext[5];
+    if (left_edge && !prev_lds) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) eprev[k] = ld_elem<C>(src, rb[kPlusX[k]] + xl);
+    }
+    if (right_edge && !next_lds) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) enext[k] = ld_elem<C>(src, rb[kMinusX[k]] + xr);
+    }
+    const int rit = (int)(g.row - g.row0);  // row within the tile
     if (a.lds_edges) {
         __syncthreads();  // the previous readers are done
         if (row_end) {
+            // site nx - 1, as the upper half of a dword for 16-bit codecs
 #pragma unroll
-            for (int k = 0; k < 5; ++k) lds.row_last[rit][k] = d[kPlusX[k]].w[NW - 1];
+            for (int k = 0; k < 5; ++k) {
+                uint32_t v = d[kPlusX[k]].w[NW - 1];
+                if constexpr (kPadded) {
+#pragma unroll
+                    for (int e = 0; e < V; ++e)
+                        if (x0 + e + 1 == nx) v = vget<C, NW>(d[kPlusX[k]], e) << (K::kBytes == 2 ? 16 : 0);
+                }
+                lds.row_last[rit][k] = v;
+            }
         }
         if (x0 == 0) {
 #pragma unroll
@@ -989,7 +1003,7 @@ __device__ __forceinline__ uint32_t gather(const StepArgs &a, const char *src, c
         const int i = kPlusX[k];  // c_x = +1: pull from x - 1
         uint32_t prev = wave_shr1(d[i].w[NW - 1]);
         if (left_edge) {
-            if (a.lds_edges) {
+            if (prev_lds) {
                 prev = x0 == 0 ? lds.row_last[rit][k] : lds.wave_last[wave - 1][k];
             } else {
                 prev = eprev[k];
@@ -1004,7 +1018,7 @@ __device__ __forceinline__ uint32_t gather(const StepArgs &a, const char *src, c
         const int i = kMinusX[k];  // c_x = -1: pull from x + 1
         uint32_t next = wave_shl1(d[i].w[0]);
         if (right_edge) {
-            if (a.lds_edges)
+            if (next_lds)
                 next = row_end ? lds.row_first[rit][k] : lds.wave_first[wave + 1][k];
             else
                 next = enext[k];

@@ -109,8 +109,8 @@ struct StepArgs {
     Layout lay;
     int nx, ny, nz;
     int nslots;               // rows * pitch / sites_per_thread
-    int lds_edges;            // 1: every tile holds whole x-rows (x-edge elements via LDS)
-    int lg_row_lanes;         // log2(lanes per x-row) when lds_edges
+    int lds_edges;            // 1: x-edge elements held by a lane of the same tile pass through LDS
+    int lg_row_lanes;         // log2(lanes per x-row) (in-place steps: every tile holds whole rows)
     int tile_order;           // 0: tile = workgroup index; 1: contiguous tile ranges per XCD
     FastDiv div_pitch, div_ny;
     Coll coll;
