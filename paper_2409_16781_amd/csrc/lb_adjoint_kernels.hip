@@ -12,8 +12,11 @@ namespace {
 // nu_n = (dC/df)^T lam_{n+1} at every site, where f = P S_n.  The kernel of
 // step n gathers lam_{n+1} = P^T nu_{n+1} (the transposed pull of the
 // previous adjoint array; for the last step lam_N is read at the site
-// itself), gathers f from S_n, and writes nu_n.  With rho, u the moments of f
-// (u with the half-force shift), w_i the weights and F the site's force:
+// itself) and writes nu_n.  The Jacobian of C at a site depends on f only
+// through its moments rho and u (u with the half-force shift), which the
+// forward step of step n wrote beside its new state; the kernel reads those
+// four floats instead of gathering f again.  With w_i the weights and F the
+// site's force:
 //   nu_j = (1 - omega) lam_j + A + B.(c_j - u) / rho
 //   A    = omega sum_i lam_i w_i (1 + 3 c_i.u + 9/2 (c_i.u)^2 - 3/2 u.u)
 //   B    = sum_i lam_i w_i c_i [3 omega rho + 9 omega rho c_i.u + 9 (1 - omega/2) c_i.F]
@@ -34,46 +37,43 @@ __global__ __launch_bounds__(kBlock) void adjoint_vec(AdjArgs a)
     const Coll &cp = sa.coll;
     const float om = 2.0f * cp.hom;        // omega
     const float k1 = 1.0f - cp.hom;        // 1 - omega/2
-    const char *state = reinterpret_cast<const char *>(a.state);
     const char *lam_src = reinterpret_cast<const char *>(a.lam_in);
     char *nu_out = reinterpret_cast<char *>(a.nu_out);
+    const size_t n = (size_t)sa.nx * sa.ny * sa.nz;
     const int ntiles = (sa.nslots + kBlock - 1) / kBlock;
     if (const int b = blockIdx.x; b < ntiles) {  // one workgroup per tile
         const TileGeom g = tile_geom<V, false>(sa, b);
-        Lane<NW> d[kQ];
-        const uint32_t dead = gather<kF32, NW, kSolids, false, false>(sa, state, g, d, lds);
-        // moments of the pulled pre-collision populations (shifted storage)
+        // the moments of step n's pulled populations, as its forward step
+        // computed them (site order; zero at solid sites)
         float rho[V], ux[V], uy[V], uz[V], fx[V];
-        float fxf[V];
+        load_masks<V>(reinterpret_cast<const uint32_t *>(a.mom) + g.s0, reinterpret_cast<uint32_t(&)[V]>(rho));
+        load_masks<V>(reinterpret_cast<const uint32_t *>(a.mom + n) + g.s0, reinterpret_cast<uint32_t(&)[V]>(ux));
+        load_masks<V>(reinterpret_cast<const uint32_t *>(a.mom + 2 * n) + g.s0, reinterpret_cast<uint32_t(&)[V]>(uy));
+        load_masks<V>(reinterpret_cast<const uint32_t *>(a.mom + 3 * n) + g.s0, reinterpret_cast<uint32_t(&)[V]>(uz));
         if (sa.fx_field)
-            load_masks<V>(reinterpret_cast<const uint32_t *>(sa.fx_field) + g.s0, reinterpret_cast<uint32_t(&)[V]>(fxf));
+            load_masks<V>(reinterpret_cast<const uint32_t *>(sa.fx_field) + g.s0, reinterpret_cast<uint32_t(&)[V]>(fx));
 #pragma unroll
-        for (int e = 0; e < V; ++e) {
-            float gg[kQ];
-#pragma unroll
-            for (int i = 0; i < kQ; ++i) gg[i] = K::dec(d[i].w[e]);
-            float dr = 0.0f, jx = 0.0f, jy = 0.0f, jz = 0.0f;
-#pragma unroll
-            for (int i = 0; i < kQ; ++i) {
-                dr += gg[i];
-                if (CX[i]) jx += CX[i] * gg[i];
-                if (CY[i]) jy += CY[i] * gg[i];
-                if (CZ[i]) jz += CZ[i] * gg[i];
-            }
-            fx[e] = cp.fx + (sa.fx_field ? fxf[e] : 0.0f);
-            rho[e] = 1.0f + dr;
-            const float inv = 1.0f / rho[e];
-            ux[e] = (jx + 0.5f * fx[e]) * inv;
-            uy[e] = (jy + cp.hfy) * inv;
-            uz[e] = (jz + cp.hfz) * inv;
-        }
+        for (int e = 0; e < V; ++e) fx[e] = cp.fx + (sa.fx_field ? fx[e] : 0.0f);
         // adjoint of the next state at this step's sites
+        Lane<NW> d[kQ];
+        uint32_t dead = 0;
         if constexpr (kFirst) {
 #pragma unroll
             for (int i = 0; i < kQ; ++i) d[i] = ldv<NW>(lam_src + (g.own + i * sa.lay.seg) * K::kBytes);
+            if constexpr (kSolids) {
+                if (wave_dirty(sa, g)) {
+                    uint32_t m[V];
+                    load_masks<V>(sa.nbmask + g.s0, m);
+#pragma unroll
+                    for (int e = 0; e < V; ++e) dead |= (m[e] >> 31) << e;
+                }
+            }
         } else {
-            (void)gather<kF32, NW, kSolids, false, true>(sa, lam_src, g, d, lds);
+            dead = gather<kF32, NW, kSolids, false, true>(sa, lam_src, g, d, lds);
         }
+#pragma unroll
+        for (int e = 0; e < V; ++e)
+            if ((dead >> e) & 1u) rho[e] = 1.0f;  // solid: no moments; the site's output is zero below
         float gF[V];
 #pragma unroll
         for (int e = 0; e < V; ++e) {

@@ -100,6 +100,8 @@ struct lb_lattice {
     long long steps;
     RunGraphs graphs;
     std::vector<void *> adj_ws;  // state-sized buffers of the adjoint sweep, kept for later calls
+    float *adj_mom;              // the sweep's per-step moments (adj_mom_steps x 4 N floats), kept likewise
+    int adj_mom_steps;
     double *jval;     // device double: the outlet flux objective
     int dev;          // HIP device the lattice lives on
     // scaled 16-bit storage (LB_S16): exponents, their device-side constants,
@@ -286,8 +288,10 @@ int enqueue_steps(lb_lattice *h, int n, float *rho, float *u);
 
 // count steps from buf[from] as one run with chained totals.  path (count + 1
 // arrays, or NULL for the A/B pair): step k reads path[k] and writes
-// path[k + 1].
-int enqueue_run(lb_lattice *h, int from, int count, hipStream_t s, const TotalsBufs &tb, void *const *path = nullptr);
+// path[k + 1].  mom (count pointers, or NULL): step k also writes its moments
+// (rho, then u_x, u_y, u_z, N floats each, site order) to mom[k].
+int enqueue_run(lb_lattice *h, int from, int count, hipStream_t s, const TotalsBufs &tb, void *const *path = nullptr,
+                float *const *mom = nullptr);
 
 // Wait for the lattice's work; if a scaled-storage step overflowed, widen
 // the range of each weight class whose codes left it by one bit
@@ -364,10 +368,11 @@ int enqueue_one(lb_lattice *h, int from, float *rho, float *u, hipStream_t s, co
 // partials into buffer k & 1, the first workgroup of step k + 1 appends the
 // totals of step k, and one totals kernel closes the run.  The ring then
 // holds the same values as with a totals kernel after every step.
-int enqueue_run(lb_lattice *h, int from, int count, hipStream_t s, const TotalsBufs &tb, void *const *path)
+int enqueue_run(lb_lattice *h, int from, int count, hipStream_t s, const TotalsBufs &tb, void *const *path,
+                float *const *mom)
 {
     if (h->inplace || h->variant == 0) {
-        if (path) return fail(LB_EINVAL, "explicit step buffers need the two-array row kernels");
+        if (path || mom) return fail(LB_EINVAL, "explicit step buffers need the two-array row kernels");
         for (int k = 0; k < count; ++k) {
             int rc = enqueue_one(h, from ^ (k & 1), nullptr, nullptr, s, tb);
             if (rc) return rc;
@@ -375,14 +380,14 @@ int enqueue_run(lb_lattice *h, int from, int count, hipStream_t s, const TotalsB
         return LB_OK;
     }
     for (int k = 0; k < count; ++k) {
-        StepArgs a = step_args(h, from ^ (k & 1), nullptr, nullptr);
+        StepArgs a = step_args(h, from ^ (k & 1), mom ? mom[k] : nullptr, mom ? mom[k] + h->n : nullptr);
         if (path) {
             a.src = path[k];
             a.dst = path[k + 1];
         }
         a.partials = tb.partials + (size_t)(k & 1) * 4 * h->grid;
         if (k > 0) a.prev = totals_args(h, (k - 1) & 1, tb, from ^ ((k - 1) & 1));
-        HIP_OR_FAIL(launch_step(h->codec, h->variant, h->solids, false, a, h->grid, s));
+        HIP_OR_FAIL(launch_step(h->codec, h->variant, h->solids, mom != nullptr, a, h->grid, s));
     }
     HIP_OR_FAIL(launch_totals(totals_args(h, (count - 1) & 1, tb, from ^ ((count - 1) & 1)), s));
     return LB_OK;
@@ -471,6 +476,9 @@ void release(lb_lattice *h)
         if (p) (void)hipFree(p);
     for (void *p : h->adj_ws) (void)hipFree(p);
     h->adj_ws.clear();
+    if (h->adj_mom) (void)hipFree(h->adj_mom);
+    h->adj_mom = nullptr;
+    h->adj_mom_steps = 0;
 }
 
 int create_impl(lb_lattice **out, int nx, int ny, int nz, double tau, const uint8_t *flags, int storage,
@@ -879,10 +887,8 @@ int grad_impl(lb_lattice *h, int nsteps, int every, const float *seed, float *gr
     if (nsteps < 1 || every < 1) return fail(LB_EINVAL, "nsteps and every must be >= 1");
     if (!grad) return fail(LB_EINVAL, "grad must be a device pointer");
     if (h->variant == 0) return fail(LB_EINVAL, "the adjoint runs the row kernels: set a force field first");
-    // sites per lane of the adjoint kernel: one (4-byte accesses; with its two
-    // gathers and the Jacobian the kernel then fits four waves per SIMD and
-    // ran fastest: 175 / 214 / 238 ms per 500-step 128^3 gradient with 1 / 2 /
-    // 4 sites per lane); LB_ADJ_KERNEL (1, 2, 3) overrides
+    // sites per lane of the adjoint kernel: one (4-byte accesses) ran fastest
+    // on the porous channels; LB_ADJ_KERNEL (1, 2, 3: four, two, one) overrides
     int av = (int)env_long("LB_ADJ_KERNEL", 0);
     if (av < 1 || av > 3) av = 3;
     while (av < 3 && h->nx % sites_per_thread(kF32, av) != 0) ++av;
@@ -890,82 +896,97 @@ int grad_impl(lb_lattice *h, int nsteps, int every, const float *seed, float *gr
     const size_t abytes = (size_t)h->arr_elems * sizeof(float);
     const int nck = (nsteps + every - 1) / every;
     const int seg = std::min(every, nsteps);
-    // device memory of the sweep: checkpoints, one segment of states, two
-    // adjoint arrays and the seed; the buffers are kept by the lattice and
-    // reused by later calls that need no more of them
-    const size_t need = (size_t)nck + (size_t)(seg - 1) + 3;
+    // Device memory of the sweep: the checkpoints, two states for the
+    // recomputed stretches, the two adjoint arrays (the first also takes the
+    // seed), and the moments of one stretch's steps (16 bytes per site and
+    // step).  The buffers are kept by the lattice and reused by later calls
+    // that need no more of them.
+    const size_t need = (size_t)nck + 4;
     while (h->adj_ws.size() < need) {
         void *p = nullptr;
         if (hipMalloc(&p, abytes) != hipSuccess)
             return fail(LB_ENOMEM, "hipMalloc of the adjoint sweep (%zu states of %zu bytes)", need, abytes);
         h->adj_ws.push_back(p);
     }
+    if (h->adj_mom_steps < seg) {
+        HIP_OR_FAIL(hipStreamSynchronize(h->stream));
+        if (h->adj_mom) (void)hipFree(h->adj_mom);
+        h->adj_mom = nullptr;
+        h->adj_mom_steps = 0;
+        void *p = nullptr;
+        if (hipMalloc(&p, (size_t)seg * 4 * h->n * sizeof(float)) != hipSuccess)
+            return fail(LB_ENOMEM, "hipMalloc of the adjoint sweep's moments (%d steps of %zu sites)", seg,
+                        (size_t)h->n);
+        h->adj_mom = static_cast<float *>(p);
+        h->adj_mom_steps = seg;
+    }
     size_t next = 0;
     auto grab = [&]() { return static_cast<char *>(h->adj_ws[next++]); };
-    auto cleanup = [&]() { (void)hipStreamSynchronize(h->stream); };
-    std::vector<char *> ck(nck), states(seg);
+    std::vector<char *> ck(nck);
     for (int k = 0; k < nck; ++k) ck[k] = grab();
-    for (int k = 1; k < seg; ++k) states[k] = grab();
+    char *tmp[2] = {grab(), grab()};
     char *nu[2] = {grab(), grab()};
-    char *lamN = grab();
+    std::vector<float *> mom(seg);
+    for (int j = 0; j < seg; ++j) mom[j] = h->adj_mom + (size_t)j * 4 * h->n;
     int rc = LB_OK;
     auto hip = [&](hipError_t e, const char *what) {
         if (rc == LB_OK && e != hipSuccess) rc = fail(LB_EHIP, "%s: %s", what, hipGetErrorString(e));
     };
-    // forward: a checkpoint, then the segment's ordinary steps as one run
-    // (chained totals); the lattice ends at step nsteps.  The last segment's
-    // intermediate states are written to the sweep's state buffers, so the
-    // backward pass need not recompute that segment.
+    // Forward: the ordinary steps as runs with chained totals, one run per
+    // stretch.  Each stretch starts from its checkpoint and its last step
+    // writes the next checkpoint (the first is a copy of the starting
+    // state), so no checkpoint is copied; the last stretch ends in the
+    // lattice's array for step nsteps and also writes the moments of its
+    // steps, so the backward pass need not recompute it.
+    const int final_cur = h->cur ^ (nsteps & 1);
+    hip(hipMemcpyAsync(ck[0], h->buf[h->cur], abytes, hipMemcpyDeviceToDevice, h->stream), "checkpoint");
     for (int k = 0; k < nck && rc == LB_OK; ++k) {
         const int len = std::min(every, nsteps - k * every);
-        hip(hipMemcpyAsync(ck[k], h->buf[h->cur], abytes, hipMemcpyDeviceToDevice, h->stream), "checkpoint");
-        if (rc == LB_OK && k == nck - 1) {
-            std::vector<void *> path(len + 1);
-            path[0] = h->buf[h->cur];
-            for (int j = 1; j < len; ++j) path[j] = states[j];
-            path[len] = h->buf[h->cur ^ (len & 1)];
-            rc = enqueue_run(h, h->cur, len, h->stream, own_bufs(h), path.data());
-        } else if (rc == LB_OK) {
-            rc = enqueue_run(h, h->cur, len, h->stream, own_bufs(h));
-        }
-        if (rc == LB_OK) {
-            h->cur ^= len & 1;
-            h->steps += len;
-        }
+        const bool last = k == nck - 1;
+        std::vector<void *> path(len + 1);
+        path[0] = ck[k];
+        for (int j = 1; j < len; ++j) path[j] = tmp[j & 1];
+        path[len] = last ? h->buf[final_cur] : ck[k + 1];
+        rc = enqueue_run(h, h->cur, len, h->stream, own_bufs(h), path.data(), last ? mom.data() : nullptr);
     }
-    // the objective of the final state: J, and its seed in the storage layout
+    if (rc == LB_OK) {
+        h->cur = final_cur;
+        h->steps += nsteps;
+    }
+    // the objective of the final state: J, and its seed dJ/dS_N (storage
+    // layout) in the first adjoint array
     if (rc == LB_OK && !seed && J) rc = outlet_flux_value(h, J);
-    if (rc == LB_OK) hip(hipMemsetAsync(lamN, 0, abytes, h->stream), "hipMemsetAsync");
+    if (rc == LB_OK) hip(hipMemsetAsync(nu[0], 0, abytes, h->stream), "hipMemsetAsync");
     if (rc == LB_OK) {
         if (seed) {
-            hip(launch_repack(const_cast<float *>(seed), lamN, h->lay, (int64_t)h->n, 4, true, h->stream), "seed");
+            hip(launch_repack(const_cast<float *>(seed), nu[0], h->lay, (int64_t)h->n, 4, true, h->stream), "seed");
         } else {
             OutletArgs oa = outlet_args(h, nullptr);
-            oa.seed = reinterpret_cast<float *>(lamN);
+            oa.seed = reinterpret_cast<float *>(nu[0]);
             hip(launch_outlet_seed(oa, h->stream), "outlet seed");
         }
     }
     if (rc == LB_OK) hip(hipMemsetAsync(grad, 0, h->n * sizeof(float), h->stream), "hipMemsetAsync");
-    if (rc == LB_OK) hip(hipMemsetAsync(nu[0], 0, abytes, h->stream), "hipMemsetAsync");
     if (rc == LB_OK) hip(hipMemsetAsync(nu[1], 0, abytes, h->stream), "hipMemsetAsync");
-    // backward, segment by segment from the last; each segment but the last
-    // is recomputed from its checkpoint (recomputed steps write no totals)
+    // Backward, stretch by stretch from the last.  Each stretch but the last
+    // is recomputed from its checkpoint through the two scratch states,
+    // keeping only its steps' moments (recomputed steps write no totals);
+    // the adjoint steps then run backwards through those moments.
     int cur_nu = 0;
     bool first = true;
     for (int k = nck - 1; k >= 0 && rc == LB_OK; --k) {
         const int start = k * every, stop = std::min(start + every, nsteps);
-        states[0] = ck[k];
-        for (int j = 1; j < stop - start && rc == LB_OK && k < nck - 1; ++j) {
-            StepArgs a = step_args(h, 0, nullptr, nullptr);
-            a.src = states[j - 1];
-            a.dst = states[j];
-            hip(launch_step(h->codec, h->variant, h->solids, false, a, h->grid, h->stream), "recompute step");
+        for (int j = 0; j < stop - start && rc == LB_OK && k < nck - 1; ++j) {
+            StepArgs a = step_args(h, 0, mom[j], mom[j] + h->n);
+            a.src = j == 0 ? ck[k] : tmp[(j - 1) & 1];
+            a.dst = tmp[j & 1];
+            hip(launch_step(h->codec, h->variant, h->solids, true, a, h->grid, h->stream), "recompute step");
         }
         for (int n = stop - 1; n >= start && rc == LB_OK; --n) {
             AdjArgs a{};
             a.s = step_args(h, 0, nullptr, nullptr, av);
-            a.state = states[n - start];
-            a.lam_in = first ? static_cast<const void *>(lamN) : nu[cur_nu];
+            a.mom = mom[n - start];
+            a.lam_in = nu[cur_nu];
             a.nu_out = nu[cur_nu ^ 1];
             a.grad = grad;
             hip(launch_adjoint(av, first, a, adj_grid, h->stream), "adjoint step");
@@ -978,7 +999,7 @@ int grad_impl(lb_lattice *h, int nsteps, int every, const float *seed, float *gr
         oa.grad = grad;
         hip(launch_outlet_direct(oa, h->stream), "outlet direct term");
     }
-    cleanup();
+    (void)hipStreamSynchronize(h->stream);
     return rc;
 }
 

@@ -161,10 +161,11 @@ struct BatchArgs {
     BatchTotalsArgs prev;     // prev.partials != nullptr: workgroup 0 also appends the previous step's totals
 };
 
-// One adjoint step (FP32 storage): see adjoint_vec in lb_kernels.hip.
+// One adjoint step (FP32 storage): see adjoint_vec in lb_adjoint_kernels.hip.
 struct AdjArgs {
     StepArgs s;               // geometry, masks, collision constants, force field
-    const void *state;        // S_n, the stored state the step starts from
+    const float *mom;         // moments of step n's pulled populations, site order: rho (N floats),
+                              // then u_x, u_y, u_z (N floats each), as written by its forward step
     const void *lam_in;       // first step: dJ/dS_N (read at each site); else nu_{n+1}
     void *nu_out;             // nu_n = (dC/df)^T lam_{n+1}
     float *grad;              // N floats (site order): += dJ/dF_x of this step
