@@ -39,17 +39,20 @@ __global__ __launch_bounds__(kBlock) void adjoint_vec(AdjArgs a)
     const float k1 = 1.0f - cp.hom;        // 1 - omega/2
     const char *lam_src = reinterpret_cast<const char *>(a.lam_in);
     char *nu_out = reinterpret_cast<char *>(a.nu_out);
-    const size_t n = (size_t)sa.nx * sa.ny * sa.nz;
     const int ntiles = (sa.nslots + kBlock - 1) / kBlock;
     if (const int b = blockIdx.x; b < ntiles) {  // one workgroup per tile
         const TileGeom g = tile_geom<V, false>(sa, b);
         // the moments of step n's pulled populations, as its forward step
-        // computed them (site order; zero at solid sites)
+        // computed them (one record per site; zero at solid sites)
         float rho[V], ux[V], uy[V], uz[V], fx[V];
-        load_masks<V>(reinterpret_cast<const uint32_t *>(a.mom) + g.s0, reinterpret_cast<uint32_t(&)[V]>(rho));
-        load_masks<V>(reinterpret_cast<const uint32_t *>(a.mom + n) + g.s0, reinterpret_cast<uint32_t(&)[V]>(ux));
-        load_masks<V>(reinterpret_cast<const uint32_t *>(a.mom + 2 * n) + g.s0, reinterpret_cast<uint32_t(&)[V]>(uy));
-        load_masks<V>(reinterpret_cast<const uint32_t *>(a.mom + 3 * n) + g.s0, reinterpret_cast<uint32_t(&)[V]>(uz));
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            const float4 m = *reinterpret_cast<const float4 *>(a.mom + 4 * (size_t)(g.s0 + e));
+            rho[e] = m.x;
+            ux[e] = m.y;
+            uy[e] = m.z;
+            uz[e] = m.w;
+        }
         if (sa.fx_field)
             load_masks<V>(reinterpret_cast<const uint32_t *>(sa.fx_field) + g.s0, reinterpret_cast<uint32_t(&)[V]>(fx));
 #pragma unroll
@@ -146,36 +149,53 @@ __device__ __forceinline__ bool outlet_fluid(const OutletArgs &a, uint32_t row, 
     return !(a.flags && a.flags[site]);
 }
 
-// One workgroup: each thread sums its rows in order, then a fixed LDS tree.
-template <int C>
-__global__ __launch_bounds__(kBlock) void outlet_flux_kernel(OutletArgs a)
+// Fixed LDS tree over the workgroup's values (same order on every run).
+__device__ __forceinline__ double block_tree_sum(double v, double (&red)[kBlock])
 {
-    using K = Codec<C>;
-    __shared__ double red[kBlock];
-    const char *src = reinterpret_cast<const char *>(a.state);
-    const uint32_t rows = (uint32_t)a.ny * (uint32_t)a.nz;
-    double acc = 0.0;
-    for (uint32_t r = threadIdx.x; r < rows; r += kBlock) {
-        uint64_t site;
-        if (!outlet_fluid(a, r, site)) continue;
-        const uint64_t own = a.lay.row_base(r) + (uint64_t)(a.nx - 1);
-        double jx = 0.0;
-#pragma unroll
-        for (int i = 0; i < kQ; ++i) {
-            if (CX[i] == 0) continue;
-            const double v = (double)K::dec(ld_elem<C>(src, own + i * a.lay.seg));
-            jx = CX[i] > 0 ? jx + v : jx - v;
-        }
-        const double F = (double)a.fx + (a.fx_field ? (double)a.fx_field[site] : 0.0);
-        acc += jx - 0.5 * F;
-    }
-    red[threadIdx.x] = acc;
+    red[threadIdx.x] = v;
     __syncthreads();
     for (int w = kBlock / 2; w >= 1; w >>= 1) {
         if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) a.J[0] = red[0];
+    return red[0];
+}
+
+// First pass: one row (its site x = nx - 1) per thread; workgroup b writes
+// the sum of its rows to part[b].
+template <int C>
+__global__ __launch_bounds__(kBlock) void outlet_flux_rows(OutletArgs a)
+{
+    using K = Codec<C>;
+    __shared__ double red[kBlock];
+    const char *src = reinterpret_cast<const char *>(a.state);
+    const uint32_t rows = (uint32_t)a.ny * (uint32_t)a.nz;
+    const uint32_t r = blockIdx.x * kBlock + threadIdx.x;
+    double acc = 0.0;
+    uint64_t site;
+    if (r < rows && outlet_fluid(a, r, site)) {
+        const uint64_t own = a.lay.row_base(r) + (uint64_t)(a.nx - 1);
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) {
+            if (CX[i] == 0) continue;
+            const double v = (double)K::dec(ld_elem<C>(src, own + i * a.lay.seg));
+            acc = CX[i] > 0 ? acc + v : acc - v;
+        }
+        acc -= 0.5 * ((double)a.fx + (a.fx_field ? (double)a.fx_field[site] : 0.0));
+    }
+    const double sum = block_tree_sum(acc, red);
+    if (threadIdx.x == 0) a.part[blockIdx.x] = sum;
+}
+
+// Second pass (one workgroup): each thread sums its share of the parts in
+// order, then the tree; J = the total.
+__global__ __launch_bounds__(kBlock) void outlet_flux_total(OutletArgs a, int nparts)
+{
+    __shared__ double red[kBlock];
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < nparts; k += kBlock) acc += a.part[k];
+    const double sum = block_tree_sum(acc, red);
+    if (threadIdx.x == 0) a.J[0] = sum;
 }
 
 // dJ/dS_N: c_ix at population i of each outlet fluid site (the rest of the
@@ -204,11 +224,16 @@ __global__ __launch_bounds__(kBlock) void outlet_direct_kernel(OutletArgs a)
 
 }  // namespace
 
+int outlet_parts(int ny, int nz) { return (int)(((uint64_t)ny * (uint64_t)nz + kBlock - 1) / kBlock); }
+
 hipError_t launch_outlet_flux(int codec, const OutletArgs &a, hipStream_t s)
 {
-    if (codec == kF32) outlet_flux_kernel<kF32><<<1, kBlock, 0, s>>>(a);
-    else if (codec == kF16) outlet_flux_kernel<kF16><<<1, kBlock, 0, s>>>(a);
-    else outlet_flux_kernel<kBF16><<<1, kBlock, 0, s>>>(a);
+    const int parts = outlet_parts(a.ny, a.nz);
+    if (codec == kF32) outlet_flux_rows<kF32><<<parts, kBlock, 0, s>>>(a);
+    else if (codec == kF16) outlet_flux_rows<kF16><<<parts, kBlock, 0, s>>>(a);
+    else outlet_flux_rows<kBF16><<<parts, kBlock, 0, s>>>(a);
+    if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
+    outlet_flux_total<<<1, kBlock, 0, s>>>(a, parts);
     return hipGetLastError();
 }
 

@@ -102,7 +102,7 @@ struct lb_lattice {
     std::vector<void *> adj_ws;  // state-sized buffers of the adjoint sweep, kept for later calls
     float *adj_mom;              // the sweep's per-step moments (adj_mom_steps x 4 N floats), kept likewise
     int adj_mom_steps;
-    double *jval;     // device double: the outlet flux objective
+    double *jval;     // device doubles: the outlet flux objective, then the parts of its sum
     int dev;          // HIP device the lattice lives on
     // scaled 16-bit storage (LB_S16): exponents, their device-side constants,
     // the two per-parity overflow flags and the last settled point (steps and
@@ -289,7 +289,7 @@ int enqueue_steps(lb_lattice *h, int n, float *rho, float *u);
 // count steps from buf[from] as one run with chained totals.  path (count + 1
 // arrays, or NULL for the A/B pair): step k reads path[k] and writes
 // path[k + 1].  mom (count pointers, or NULL): step k also writes its moments
-// (rho, then u_x, u_y, u_z, N floats each, site order) to mom[k].
+// (one record rho, u_x, u_y, u_z per site, site order) to mom[k].
 int enqueue_run(lb_lattice *h, int from, int count, hipStream_t s, const TotalsBufs &tb, void *const *path = nullptr,
                 float *const *mom = nullptr);
 
@@ -380,7 +380,8 @@ int enqueue_run(lb_lattice *h, int from, int count, hipStream_t s, const TotalsB
         return LB_OK;
     }
     for (int k = 0; k < count; ++k) {
-        StepArgs a = step_args(h, from ^ (k & 1), mom ? mom[k] : nullptr, mom ? mom[k] + h->n : nullptr);
+        StepArgs a = step_args(h, from ^ (k & 1), mom ? mom[k] : nullptr, nullptr);
+        a.mom_rec = mom ? 1 : 0;
         if (path) {
             a.src = path[k];
             a.dst = path[k + 1];
@@ -642,7 +643,9 @@ int create_impl(lb_lattice **out, int nx, int ny, int nz, double tau, const uint
     if ((e = hipMalloc(&h->ticket, sizeof(unsigned int))) != hipSuccess) return bail(LB_ENOMEM, "hipMalloc", e);
     if ((e = hipMalloc(&h->ring, (size_t)kRingCap * 4 * sizeof(double))) != hipSuccess) return bail(LB_ENOMEM, "hipMalloc", e);
     if ((e = hipMalloc(&h->counter, sizeof(unsigned long long))) != hipSuccess) return bail(LB_ENOMEM, "hipMalloc", e);
-    if ((e = hipMalloc(&h->jval, 256)) != hipSuccess) return bail(LB_ENOMEM, "hipMalloc", e);
+    // J, then the per-workgroup parts of its sum
+    if ((e = hipMalloc(&h->jval, (1 + (size_t)outlet_parts(ny, nz)) * sizeof(double))) != hipSuccess)
+        return bail(LB_ENOMEM, "hipMalloc", e);
     if ((e = hipMemsetAsync(h->ticket, 0, sizeof(unsigned int), h->stream)) != hipSuccess) return bail(LB_EHIP, "hipMemsetAsync", e);
     if ((e = hipMemsetAsync(h->counter, 0, sizeof(unsigned long long), h->stream)) != hipSuccess) return bail(LB_EHIP, "hipMemsetAsync", e);
     if ((e = hipMemsetAsync(h->ring, 0, (size_t)kRingCap * 4 * sizeof(double), h->stream)) != hipSuccess) return bail(LB_EHIP, "hipMemsetAsync", e);
@@ -856,6 +859,7 @@ OutletArgs outlet_args(const lb_lattice *h, const void *state)
     OutletArgs a{};
     a.state = state;
     a.J = h->jval;
+    a.part = h->jval + 1;
     a.lay = h->lay;
     a.nx = h->nx;
     a.ny = h->ny;
@@ -898,8 +902,8 @@ int grad_impl(lb_lattice *h, int nsteps, int every, const float *seed, float *gr
     const int seg = std::min(every, nsteps);
     // Device memory of the sweep: the checkpoints, two states for the
     // recomputed stretches, the two adjoint arrays (the first also takes the
-    // seed), and the moments of one stretch's steps (16 bytes per site and
-    // step).  The buffers are kept by the lattice and reused by later calls
+    // seed), and the moments of one stretch's steps (a 16-byte record per
+    // site and step).  The buffers are kept by the lattice and reused by later calls
     // that need no more of them.
     const size_t need = (size_t)nck + 4;
     while (h->adj_ws.size() < need) {
@@ -977,9 +981,11 @@ int grad_impl(lb_lattice *h, int nsteps, int every, const float *seed, float *gr
     for (int k = nck - 1; k >= 0 && rc == LB_OK; --k) {
         const int start = k * every, stop = std::min(start + every, nsteps);
         for (int j = 0; j < stop - start && rc == LB_OK && k < nck - 1; ++j) {
-            StepArgs a = step_args(h, 0, mom[j], mom[j] + h->n);
+            StepArgs a = step_args(h, 0, mom[j], nullptr);
+            a.mom_rec = 1;
             a.src = j == 0 ? ck[k] : tmp[(j - 1) & 1];
-            a.dst = tmp[j & 1];
+            // the stretch's last state is not needed: that step writes its moments only
+            a.dst = j + 1 < stop - start ? tmp[j & 1] : nullptr;
             hip(launch_step(h->codec, h->variant, h->solids, true, a, h->grid, h->stream), "recompute step");
         }
         for (int n = stop - 1; n >= start && rc == LB_OK; --n) {

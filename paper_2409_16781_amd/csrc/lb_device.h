@@ -1227,18 +1227,24 @@ __device__ __forceinline__ void tile_update(const StepArgs &a, const char *src, 
                 }
             }
         }
-        if (dead != (1u << V) - 1u) {
+        if (dead != (1u << V) - 1u && (!kMacros || dst != nullptr)) {
             const StoreBase sb = store_base(dst, g.own, K::kBytes);
             const uint32_t segb = a.lay.seg * (uint32_t)K::kBytes;
 #pragma unroll
             for (int i = 0; i < kQ; ++i) stv_pop<NW>(sb, (uint32_t)i * segb, d[i]);
         }
         if constexpr (kMacros) {
-            const size_t n = (size_t)a.nx * a.ny * a.nz;
-            store_floats<V>(a.rho_out + g.s0, mr);
-            store_floats<V>(a.u_out + g.s0, mu);
-            store_floats<V>(a.u_out + n + g.s0, mv);
-            store_floats<V>(a.u_out + 2 * n + g.s0, mw);
+            if (a.mom_rec) {
+#pragma unroll
+                for (int e = 0; e < V; ++e)
+                    *reinterpret_cast<float4 *>(a.rho_out + 4 * (size_t)(g.s0 + e)) = make_float4(mr[e], mu[e], mv[e], mw[e]);
+            } else {
+                const size_t n = (size_t)a.nx * a.ny * a.nz;
+                store_floats<V>(a.rho_out + g.s0, mr);
+                store_floats<V>(a.u_out + g.s0, mu);
+                store_floats<V>(a.u_out + n + g.s0, mv);
+                store_floats<V>(a.u_out + 2 * n + g.s0, mw);
+            }
         }
         // totals of the values as stored (after rounding), fluid sites only
         add_lane_totals<C, NW>(d, acc, a.sc);

@@ -119,6 +119,9 @@ struct StepArgs {
     const uint32_t *rowcum;   // rows + 1 entries: rowcum[r] = dirty rows before row r
     float *rho_out;           // optional macros output (N floats) or nullptr
     float *u_out;             // optional macros output (3N floats) or nullptr
+    int mom_rec;              // with macros: 1 = rho_out receives one record (rho, u_x, u_y, u_z) per
+                              // site (4N floats, site order) and u_out is unused; then dst may be
+                              // nullptr (the step writes its moments only)
     double *partials;         // out: 4 doubles per workgroup
     const float *fx_field;    // optional per-site x-force added to coll.fx (N floats, site order) or nullptr
     TotalsArgs prev;          // prev.partials != nullptr: workgroup 0 also appends the totals of the
@@ -164,8 +167,8 @@ struct BatchArgs {
 // One adjoint step (FP32 storage): see adjoint_vec in lb_adjoint_kernels.hip.
 struct AdjArgs {
     StepArgs s;               // geometry, masks, collision constants, force field
-    const float *mom;         // moments of step n's pulled populations, site order: rho (N floats),
-                              // then u_x, u_y, u_z (N floats each), as written by its forward step
+    const float *mom;         // moments of step n's pulled populations: one record (rho, u_x, u_y,
+                              // u_z) per site, site order, as written by its forward step
     const void *lam_in;       // first step: dJ/dS_N (read at each site); else nu_{n+1}
     void *nu_out;             // nu_n = (dC/df)^T lam_{n+1}
     float *grad;              // N floats (site order): += dJ/dF_x of this step
@@ -178,6 +181,7 @@ struct OutletArgs {
     float *seed;              // storage-layout FP32 array: dJ/dS_N = c_ix at the outlet's fluid sites
     float *grad;              // N floats, site order: the direct term -1/2 at the outlet's fluid sites
     double *J;                // device double receiving J
+    double *part;             // outlet_parts(ny, nz) doubles: the per-workgroup sums of J
     Layout lay;
     int nx, ny, nz;
     const uint8_t *flags;     // device flags or nullptr (all fluid)
@@ -276,6 +280,7 @@ int batch_occupancy(int codec, int variant, size_t lds_pad);
 // sum), its seed dJ/dS_N written into a zeroed storage-layout array, and its
 // direct term added to a gradient.
 hipError_t launch_outlet_flux(int codec, const OutletArgs &a, hipStream_t s);
+int outlet_parts(int ny, int nz);
 hipError_t launch_outlet_seed(const OutletArgs &a, hipStream_t s);
 hipError_t launch_outlet_direct(const OutletArgs &a, hipStream_t s);
 // Raw planes (19 x n elements of esize bytes, site order) to the storage
