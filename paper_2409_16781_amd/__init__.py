@@ -308,7 +308,7 @@ class Lattice:
     @property
     def info(self) -> dict:
         keys = ["variant", "sites_per_thread", "solids", "bytes_per_population", "grid", "block_rows", "n_fluid",
-                "array_bytes", "inplace", "codec", "rescales", "tile_order"]
+                "array_bytes", "inplace", "codec", "rescales", "tile_order", "pull_nt"]
         return {k: self.query(i) for i, k in enumerate(keys)}
 
     def time_steps(self, n: int) -> float:

@@ -96,6 +96,7 @@ struct lb_lattice {
     hipStream_t stream;
     int variant, vsites, grid, cus;
     int tile_order;
+    int pull_nt;      // 1: plain steps with solids pull with non-temporal loads
     bool inplace;     // one population array (AA pattern); cur is then the phase (0 even, 1 odd)
     long long steps;
     RunGraphs graphs;
@@ -142,6 +143,7 @@ StepArgs step_args(const lb_lattice *h, int from, float *rho, float *u, int vari
     // for comparison)
     const int row_lanes = h->nx / vsites;
     a.tile_order = h->tile_order;
+    a.pull_nt = h->pull_nt;
     a.lds_edges = (variant != 0 && (h->inplace || env_long("LB_LDS_EDGES", 1) != 0)) ? 1 : 0;
     a.lg_row_lanes = 0;
     while ((1 << a.lg_row_lanes) < row_lanes) ++a.lg_row_lanes;
@@ -625,6 +627,7 @@ int create_impl(lb_lattice **out, int nx, int ny, int nz, double tau, const uint
     const long ab_off = env_long("LB_AB_OFFSET", 0);
     if (ab_off < 0 || ab_off % 256 != 0) return bail(LB_EINVAL, "LB_AB_OFFSET", hipErrorInvalidValue);
     h->tile_order = env_long("LB_TILE_ORDER", 0) != 0 ? 1 : 0;
+    h->pull_nt = env_long("LB_PULL_NT", 0) != 0 ? 1 : 0;
     hipError_t e;
     for (int b = 0; b < (h->inplace ? 1 : 2); ++b) {
         const size_t off = b == 1 ? (size_t)ab_off : 0;
@@ -1192,6 +1195,7 @@ long long lb_query(const lb_lattice *h, int key)
         case 9: return h->codec;
         case 10: return h->rescales;
         case 11: return h->tile_order;
+        case 12: return h->pull_nt;
         default: return -1;
     }
 }
@@ -1224,8 +1228,10 @@ int lb_tune(lb_lattice *h, int reps)
     if (h->inplace) return fail(LB_EINVAL, "the in-place step has one launch shape per lattice");
     if (int rc = settle(h)) return rc;
     // candidates: vector widths that divide nx, each with both tile orders
+    // and, with solids, both cache policies of the pulls (the force-field
+    // kernels always pull with cached loads)
     struct Cand {
-        int variant, order, grid;
+        int variant, order, grid, nt;
         double ms;
     };
     std::vector<Cand> cands;
@@ -1235,7 +1241,9 @@ int lb_tune(lb_lattice *h, int reps)
         if (h->nx % V != 0) continue;
         const uint64_t tiles = (h->n / V + kBlock - 1) / kBlock;
         if (tiles > 0x7fffffffull) continue;
-        for (int order = 0; order < 2; ++order) cands.push_back(Cand{v, order, (int)tiles, 0.0});
+        for (int order = 0; order < 2; ++order)
+            for (int nt = 0; nt < (h->solids && !h->ffield ? 2 : 1); ++nt)
+                cands.push_back(Cand{v, order, (int)tiles, nt, 0.0});
         max_grid = std::max(max_grid, (int)tiles);
     }
     if (cands.empty()) return LB_OK;  // only the one-site kernel fits this nx
@@ -1264,11 +1272,12 @@ int lb_tune(lb_lattice *h, int reps)
     }
     Events evs(2);
     HIP_OR_FAIL(evs.create());
-    const int saved_variant = h->variant, saved_order = h->tile_order;
+    const int saved_variant = h->variant, saved_order = h->tile_order, saved_nt = h->pull_nt;
     int rc = LB_OK;
     for (Cand &c : cands) {
         h->variant = c.variant;
         h->tile_order = c.order;
+        h->pull_nt = c.nt;
         if (hipMemsetAsync(tctr, 0, sizeof(unsigned long long), h->stream) != hipSuccess) rc = fail(LB_EHIP, "memset");
         auto launch = [&](int k) {
             StepArgs a = step_args(h, h->cur, nullptr, nullptr, c.variant);
@@ -1301,6 +1310,7 @@ int lb_tune(lb_lattice *h, int reps)
     (void)hipFree(tctr);
     h->variant = saved_variant;
     h->tile_order = saved_order;
+    h->pull_nt = saved_nt;
     if (rc != LB_OK) return rc;
     const Cand *best = &cands[0];
     for (const Cand &c : cands)
@@ -1308,6 +1318,7 @@ int lb_tune(lb_lattice *h, int reps)
     h->variant = best->variant;
     h->vsites = sites_per_thread(h->codec, best->variant);
     h->tile_order = best->order;
+    h->pull_nt = best->nt;
     h->grid = best->grid;
     h->graphs.invalidate();
     if (h->codec == kS16) HIP_OR_FAIL(launch_zero_words(h->ovf, 2, h->stream));  // timing launches may flag

@@ -57,10 +57,12 @@ struct Lane {
 #endif
 
 // kNT = false: an ordinary (cached) load.  Kernels with solid sites pull
-// with cached loads: a bounce-back load of a site's own opposite population
-// then tends to hit the L2 line that the tile pulling that population from
-// the site's row has just fetched, instead of fetching a whole line for one
-// lane's element again.
+// with cached loads by default: a bounce-back load of a site's own opposite
+// population then tends to hit the L2 line that the tile pulling that
+// population from the site's row has just fetched, instead of fetching a
+// whole line for one lane's element again.  Where few sites bounce back
+// (walls), non-temporal pulls can be faster; the launch-shape tuner times
+// both.
 template <typename T, bool kNT = true>
 __device__ __forceinline__ T ldg(const T *p)
 {
@@ -910,8 +912,9 @@ __device__ __forceinline__ bool wave_dirty(const StepArgs &a, const TileGeom &g)
 // the adjoint instead: d[i] = src_opp(i)(x - c_i), or src_i(x) where x - c_i
 // is solid (that is the value of population opp(i) of the transposed
 // streaming).  Returns the lane's dead sites (bit e: site e is solid, or
-// padding when kPadded).
-template <int C, int NW, bool kSolids, bool kPadded, bool kSwap>
+// padding when kPadded).  kPullNT: with solids, pull with non-temporal loads
+// (without solids the pulls always are).
+template <int C, int NW, bool kSolids, bool kPadded, bool kSwap, bool kPullNT = false>
 __device__ __forceinline__ uint32_t gather(const StepArgs &a, const char *src, const TileGeom &g, Lane<NW> (&d)[kQ],
                                            EdgeLds &lds)
 {
@@ -930,7 +933,7 @@ __device__ __forceinline__ uint32_t gather(const StepArgs &a, const char *src, c
         rb[i] = a.lay.row_base(zs * ny + ys) + (uint64_t)(kSwap ? OPP[i] : i) * a.lay.seg;
     }
 #pragma unroll
-    for (int i = 0; i < kQ; ++i) d[i] = ldv<NW, !kSolids>(src + (rb[i] + x0) * K::kBytes);
+    for (int i = 0; i < kQ; ++i) d[i] = ldv<NW, !kSolids || kPullNT>(src + (rb[i] + x0) * K::kBytes);
     // Waves with a dead site or a bounce-back issue their neighbour masks
     // right behind the pulls (one round trip for both); the others read no
     // mask at all.
@@ -1187,8 +1190,9 @@ __device__ __forceinline__ void s16_flag(const StepArgs &a, const Range16 &r)
 // the tile's fluid sites to acc.  kPadded: rows are stored with pitch > nx
 // (a whole number of vectors); the sites x >= nx of a row are held at zero
 // like solid sites and take no part in the totals.  kFField: the x-force of
-// each site is the uniform one plus a per-site field (a.fx_field).
-template <int C, int NW, bool kSolids, bool kMacros, bool kPadded, bool kFField = false>
+// each site is the uniform one plus a per-site field (a.fx_field).  kPullNT:
+// as in gather.
+template <int C, int NW, bool kSolids, bool kMacros, bool kPadded, bool kFField = false, bool kPullNT = false>
 __device__ __forceinline__ void tile_update(const StepArgs &a, const char *src, char *dst, int tile,
                                             double (&acc)[4], EdgeLds &lds)
 {
@@ -1199,7 +1203,7 @@ __device__ __forceinline__ void tile_update(const StepArgs &a, const char *src, 
     const Coll &cp = a.coll;
     const TileGeom g = tile_geom<V, kPadded>(a, tile);
     Lane<NW> d[kQ];
-    const uint32_t dead = gather<C, NW, kSolids, kPadded, false>(a, src, g, d, lds);
+    const uint32_t dead = gather<C, NW, kSolids, kPadded, false, kPullNT>(a, src, g, d, lds);
 
     // collide site by site (16-bit codecs: two sites per dword at a time)
     float mr[V], mu[V], mv[V], mw[V];

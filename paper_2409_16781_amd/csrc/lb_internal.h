@@ -112,6 +112,8 @@ struct StepArgs {
     int lds_edges;            // 1: x-edge elements held by a lane of the same tile pass through LDS
     int lg_row_lanes;         // log2(lanes per x-row) (in-place steps: every tile holds whole rows)
     int tile_order;           // 0: tile = workgroup index; 1: contiguous tile ranges per XCD
+    int pull_nt;              // host side: 1 = a plain step with solids runs the kernel that pulls with
+                              // non-temporal loads (launch_step picks it)
     FastDiv div_pitch, div_ny;
     Coll coll;
     const uint32_t *nbmask;   // per site: bit i = site x - c_i is solid, bit 31 = site is solid

@@ -77,7 +77,7 @@ __global__ __launch_bounds__(kBlock) void reduce_totals(TotalsArgs a)
 // of steps, workgroup 0 also appends the previous step's totals to the ring
 // (a.prev), so a run needs one totals kernel at its end instead of one per
 // step.
-template <int C, int NW, bool kSolids, bool kMacros, bool kFField = false>
+template <int C, int NW, bool kSolids, bool kMacros, bool kFField = false, bool kPullNT = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(vec_waves<C, NW>()))) void step_vec(StepArgs a)
 {
     __shared__ EdgeLds lds;
@@ -87,8 +87,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(vec_wave
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     const int ntiles = (a.nslots + kBlock - 1) / kBlock;
     if ((int)blockIdx.x < ntiles)
-        tile_update<C, NW, kSolids, kMacros, false, kFField>(a, src, dst, tile_of(blockIdx.x, ntiles, a.tile_order), acc,
-                                                             lds);
+        tile_update<C, NW, kSolids, kMacros, false, kFField, kPullNT>(a, src, dst,
+                                                                      tile_of(blockIdx.x, ntiles, a.tile_order), acc, lds);
     store_block_totals(acc, a.partials + 4 * (size_t)blockIdx.x);
     if (a.prev.partials != nullptr && blockIdx.x == 0) append_step_totals(a.prev);
 }
@@ -462,8 +462,27 @@ void *ffield_fn(int variant)
     return reinterpret_cast<void *>(&step_vec<kF32, 1, S, M, true>);
 }
 
-void *pick_step(int codec, int variant, bool solids, bool macros, bool ffield)
+// Plain steps of lattices with solids, pulling with non-temporal loads.
+template <int C>
+void *pull_nt_fn(int variant)
 {
+    if (variant == 1) return reinterpret_cast<void *>(&step_vec<C, 4, true, false, false, true>);
+    if (variant == 2) return reinterpret_cast<void *>(&step_vec<C, 2, true, false, false, true>);
+    return reinterpret_cast<void *>(&step_vec<C, 1, true, false, false, true>);
+}
+
+// pull_nt: plain steps with solids on the vector-row kernels pull with
+// non-temporal loads (ignored elsewhere)
+void *pick_step(int codec, int variant, bool solids, bool macros, bool ffield, bool pull_nt = false)
+{
+    if (pull_nt && solids && !macros && !ffield && variant != 0) {
+        switch (codec) {
+            case kF32: return pull_nt_fn<kF32>(variant);
+            case kF16: return pull_nt_fn<kF16>(variant);
+            case kS16: return pull_nt_fn<kS16>(variant);
+            default: return pull_nt_fn<kBF16>(variant);
+        }
+    }
     if (ffield) {  // FP32 storage, vector-row variants only (checked by the caller)
         if (solids) return macros ? ffield_fn<true, true>(variant) : ffield_fn<true, false>(variant);
         return macros ? ffield_fn<false, true>(variant) : ffield_fn<false, false>(variant);
@@ -526,7 +545,7 @@ int step_occupancy(int codec, int variant, bool solids, bool macros)
 
 hipError_t launch_step(int codec, int variant, bool solids, bool macros, const StepArgs &a, int grid, hipStream_t s)
 {
-    void *fn = pick_step(codec, variant, solids, macros, a.fx_field != nullptr);
+    void *fn = pick_step(codec, variant, solids, macros, a.fx_field != nullptr, a.pull_nt != 0);
     StepArgs arg = a;
     void *params[] = {&arg};
     return hipLaunchKernel(fn, dim3(grid), dim3(kBlock), params, 0, s);

@@ -7,6 +7,8 @@ where the method is a pure permutation (omega = 0) or a fixed point (rest).
 """
 import math
 
+import os
+
 import numpy as np
 import pytest
 
@@ -324,7 +326,7 @@ def test_tune_keeps_the_state_and_picks_a_valid_shape(codec):
     raw, tot = lat.get_f(), lat.sums(7)
     info = lat.tune(5)
     say(f"  {codec}: tuned shape variant={info['variant']} tile_order={info['tile_order']} grid={info['grid']}")
-    assert info["variant"] in (1, 2, 3) and info["tile_order"] in (0, 1)
+    assert info["variant"] in (1, 2, 3) and info["tile_order"] in (0, 1) and info["pull_nt"] in (0, 1)
     assert np.array_equal(lat.get_f(), raw) and np.array_equal(lat.sums(7), tot) and lat.steps_done == 7
     lat.step(43)
     _, u = lat.macros()
@@ -332,6 +334,36 @@ def test_tune_keeps_the_state_and_picks_a_valid_shape(codec):
     err = rel_l2_u(u.double().cpu().numpy(), u_ref, fluid_mask(cfg))
     assert err <= (1e-5 if codec == "f32" else 2e-3), err
     lat.close()
+
+
+@pytest.mark.parametrize("codec,variant", [("f32", 1), ("f32", 3), ("f16", 2), ("bf16", 1), ("s16", 2), ("s16", 3)])
+def test_pull_cache_policy_changes_no_bits(codec, variant):
+    """Lattices with solids pull with cached or with non-temporal loads
+    (LB_PULL_NT, a dimension of lb_tune): the same state and totals, bit for
+    bit, over single steps and a captured run."""
+    cfg = _porous(64, 20, 12, 0.15, 23)
+    lats = []
+    for nt in ("0", "1"):
+        old = os.environ.get("LB_PULL_NT")
+        os.environ["LB_PULL_NT"] = nt
+        try:
+            lat = make_lattice(cfg, codec, variant)
+        finally:
+            if old is None:
+                os.environ.pop("LB_PULL_NT", None)
+            else:
+                os.environ["LB_PULL_NT"] = old
+        assert lat.info["pull_nt"] == int(nt) and lat.info["variant"] == variant
+        say(f"[gpu] pull policy nt={nt} {codec} variant={variant}")
+        for _ in range(3):
+            lat.step(1)
+        lat.step(70)
+        lats.append(lat)
+    a, b = lats
+    assert np.array_equal(a.get_f(), b.get_f())
+    assert np.array_equal(a.sums(73).view(np.uint64), b.sums(73).view(np.uint64))
+    a.close()
+    b.close()
 
 
 @pytest.mark.parametrize("codec", ["f32", "f16", "bf16"])
