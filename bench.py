@@ -217,8 +217,9 @@ def run_inplace(torch, lbm, cfg, steps, reps):
 
 def run_adjoint(torch, lbm, reps):
     """Gradient of the outlet mass flux of a 128^3 porous channel (porosity
-    0.85) with respect to the per-site x-force: 500 forward steps with a copy
-    every 50, recomputation and 500 adjoint steps (FP32 storage)."""
+    0.85) with respect to the per-site x-force: 500 forward steps with a
+    checkpoint every 50, recomputation and 500 adjoint steps (FP32
+    storage)."""
     from paper_2409_16781_amd import inputs
     cfg = inputs.porous_channel(128, porosity=0.85, tau=0.6, g=1e-6, seed=4, steps=500, every=50)
     n = 128
@@ -230,7 +231,7 @@ def run_adjoint(torch, lbm, reps):
     lat.set_force_field(torch.zeros((n, n, n), dtype=torch.float32, device="cuda"))
     lat.init_eq(rho, u)
     shape = lat.tune(10)  # forward (and recompute) launch shape for this lattice
-    lat.grad_outlet_flux_x(20, 10)  # warm-up
+    lat.grad_outlet_flux_x(cfg["steps"], cfg["every"])  # warm-up: allocates the sweep's buffers
     times = []
     for _ in range(reps):
         lat.init_eq(rho, u)
@@ -243,10 +244,10 @@ def run_adjoint(torch, lbm, reps):
     fl = int(fluid.sum())
     lat.close()
     return dict(workload="128^3 porous channel (porosity 0.85, seed 4), tau=0.6, force 1e-6, gradient of the outlet "
-                         "mass flux w.r.t. the per-site x-force, 500 steps, copies every 50, FP32",
+                         "mass flux w.r.t. the per-site x-force, 500 steps, checkpoints every 50, FP32",
                 sites=n ** 3, fluid_sites=fl, steps=cfg["steps"], every=cfg["every"],
                 ms_per_gradient=round(dt * 1e3, 3),
-                forward_shape={k: shape[k] for k in ("variant", "sites_per_thread", "tile_order", "grid")},
+                forward_shape={k: shape[k] for k in ("variant", "sites_per_thread", "tile_order", "pull_nt", "grid")},
                 site_steps_per_s=round(3 * cfg["steps"] * n ** 3 / dt / 1e6, 1),
                 note="forward + recompute + adjoint = 3 x steps site updates; the sweep's buffers are kept by the lattice "
                      "from the warm-up call on",
@@ -317,7 +318,7 @@ def run_small(torch, lbm, reps, steps=0):
                                 gbs_algorithmic=round(bytes_per_site(codec) * nf * cfg["steps"] / (ms * 1e-3) / 1e9, 1),
                                 kernel_ms=round(kernel_ms, 5), kernel_gbs=round(kgbs, 1),
                                 kernel_frac_hbm=round(kgbs / HBM_PEAK_GBS, 4),
-                                shape={k: shape[k] for k in ("variant", "sites_per_thread", "tile_order", "grid")},
+                                shape={k: shape[k] for k in ("variant", "sites_per_thread", "tile_order", "pull_nt", "grid")},
                                 finite_totals=bool(np.all(np.isfinite(sums))))
         out[key] = entry
     return out

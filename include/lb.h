@@ -304,17 +304,20 @@ int lb_set_force_field(lb_lattice *lat, const float *fx);
  * collision Jacobian of BGK with Guo forcing and the transposed pull
  * streaming with bounce-back, one fused kernel per step).
  * The call advances the lattice by nsteps steps exactly as lb_step does
- * (state, step count and totals), keeping a copy of the state every `every`
- * steps, then sweeps backwards: each stretch of `every` steps is recomputed
- * from its copy and differentiated.  seed: caller-owned DEVICE array of
+ * (state, step count and totals), keeping the state every `every` steps
+ * (checkpoints) and the density and velocity of each step of the last
+ * stretch, then sweeps backwards: each earlier stretch of `every` steps is
+ * recomputed from its checkpoint, keeping its steps' density and velocity,
+ * and differentiated.  seed: caller-owned DEVICE array of
  * 19 * N floats in the raw-state layout of lb_get_f holding dJ/dS_N, the
  * derivative of the objective with respect to the final stored state (zero
  * at solid sites).  grad: caller-owned DEVICE array of N floats, overwritten
  * with sum over the steps of dJ/dF_x(s) through the collisions; a term of J
  * that depends on the force directly is the caller's to add.  FP32 storage.
- * Device memory for ceil(nsteps / every) + min(every, nsteps) + 2 states is
- * allocated by the first call that needs it and kept by the lattice for
- * later calls (lb_destroy frees it); the call synchronises the stream.
+ * Device memory for ceil(nsteps / every) + 4 states and 16 * N *
+ * min(every, nsteps) bytes is allocated by the first call that needs it and
+ * kept by the lattice for later calls (lb_destroy frees it); the call
+ * synchronises the stream.
  */
 int lb_grad_force_x(lb_lattice *lat, int nsteps, int every, const float *seed, float *grad);
 
