@@ -116,7 +116,8 @@ struct StepArgs {
                               // non-temporal loads (launch_step picks it)
     FastDiv div_pitch, div_ny;
     Coll coll;
-    const uint32_t *nbmask;   // per site: bit i = site x - c_i is solid, bit 31 = site is solid
+    const uint32_t *nbmask;   // per site: bit 31 = site is solid; a fluid site also has bit i set
+                              // where x - c_i is solid (a solid site has bit 31 alone)
     const uint8_t *rowdirty;  // per row (y, z): 1 if any site of the row has a bit set in nbmask
     const uint32_t *rowcum;   // rows + 1 entries: rowcum[r] = dirty rows before row r
     float *rho_out;           // optional macros output (N floats) or nullptr

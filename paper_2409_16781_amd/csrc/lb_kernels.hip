@@ -345,8 +345,11 @@ __global__ __launch_bounds__(kBlock) void build_masks(const uint8_t *flags, int 
         const int64_t row = s / pitch;
         const int y = (int)(row % ny), z = (int)(row / ny);
         uint32_t m = 0;
-        if (x < nx) {
-            m = flags[row * nx + x] ? (1u << 31) : 0u;
+        if (x < nx && flags[row * nx + x]) {
+            // a solid site takes no values from anywhere: no neighbour bits,
+            // so the gathers issue no bounce-back loads for it
+            m = 1u << 31;
+        } else if (x < nx) {
 #pragma unroll
             for (int i = 1; i < kQ; ++i) {
                 int xs = x - CX[i], ys = y - CY[i], zs = z - CZ[i];
