@@ -244,7 +244,8 @@ long long lb_steps_done(const lb_lattice *lat);
  * 5 = x-rows per storage block, 6 = number of fluid sites, 7 = bytes of one
  * population array, 8 = 1 for in-place (one-array) storage, 9 = storage
  * codec, 10 = range widenings of LB_S16 storage so far, 11 = tile order (0
- * linear, 1 a contiguous range of tiles per XCD), 12 = 1 if the steps of a
+ * linear, 1 a contiguous range of tiles per XCD, 2 linear with each block of
+ * 64 tiles rotated by its index), 12 = 1 if the steps of a
  * lattice with solids pull with non-temporal loads (else cached loads).
  * Returns -1 for an unknown key or a bad handle.
  */
@@ -266,8 +267,8 @@ int lb_time_step_kernel(lb_lattice *lat, int n, double *ms);
 
 /*
  * Launch-shape tuner: time the step kernel with every vector width that
- * divides nx (16-, 8- and 4-byte accesses per lane) and both tile orders
- * (linear, or a contiguous range of tiles per XCD), with solids also both
+ * divides nx (16-, 8- and 4-byte accesses per lane) and the three tile
+ * orders (lb_query key 11), with solids also both
  * cache policies of the pull loads (cached, or non-temporal), reps launches
  * each, and keep the fastest for this lattice (lb_query keys 0, 4, 11 and 12
  * report it).  Each

@@ -554,7 +554,8 @@ lb_batch *lb_batch_create(int count, const int *dims, const double *taus, const 
     s.grid_mult = (int)env_long("LB_BATCH_GRID", 0);
     s.tile_order = (int)env_long("LB_BATCH_TILE_ORDER", 0);
     s.wg_cap = (int)env_long("LB_BATCH_WG_CAP", 0);
-    if (s.variant < 1 || s.variant > 3 || s.seg_bytes < 64 || s.grid_mult < 0 || s.wg_cap < 0 || (s.wg_cap > 0 && s.wg_cap < 3)) {
+    if (s.variant < 1 || s.variant > 3 || s.seg_bytes < 64 || s.grid_mult < 0 || s.wg_cap < 0 || (s.wg_cap > 0 && s.wg_cap < 3) ||
+        s.tile_order < 0 || s.tile_order > 2) {
         release_all(b);
         delete b;
         fail(LB_EINVAL, "invalid LB_BATCH_* setting");

@@ -626,7 +626,10 @@ int create_impl(lb_lattice **out, int nx, int ny, int nz, double tau, const uint
     // tuning the relative placement of the two arrays in the HBM channels
     const long ab_off = env_long("LB_AB_OFFSET", 0);
     if (ab_off < 0 || ab_off % 256 != 0) return bail(LB_EINVAL, "LB_AB_OFFSET", hipErrorInvalidValue);
-    h->tile_order = env_long("LB_TILE_ORDER", 0) != 0 ? 1 : 0;
+    {
+        const long o = env_long("LB_TILE_ORDER", 0);
+        h->tile_order = o >= 0 && o <= 2 ? (int)o : 0;
+    }
     h->pull_nt = env_long("LB_PULL_NT", 0) != 0 ? 1 : 0;
     hipError_t e;
     for (int b = 0; b < (h->inplace ? 1 : 2); ++b) {
@@ -1241,7 +1244,7 @@ int lb_tune(lb_lattice *h, int reps)
         if (h->nx % V != 0) continue;
         const uint64_t tiles = (h->n / V + kBlock - 1) / kBlock;
         if (tiles > 0x7fffffffull) continue;
-        for (int order = 0; order < 2; ++order)
+        for (int order = 0; order < 3; ++order)
             for (int nt = 0; nt < (h->solids && !h->ffield ? 2 : 1); ++nt)
                 cands.push_back(Cand{v, order, (int)tiles, nt, 0.0});
         max_grid = std::max(max_grid, (int)tiles);

@@ -836,9 +836,21 @@ constexpr int vec_waves()
 // Workgroups are dispatched round-robin over the chip's 8 XCDs (workgroup b
 // runs on XCD b mod 8).  Order 1 gives each XCD a contiguous range of tiles:
 // a bijection of [0, ntiles) that leaves the last ntiles mod 8 tiles in place.
+// Order 2 keeps consecutive workgroups on consecutive tiles but rotates each
+// block of 64 tiles by the block's index, so that tiles at the same place of
+// every block (the wall rows of every plane, when a plane is 64 tiles) do
+// not all run on the same XCD.
 __device__ __forceinline__ int tile_of(int b, int ntiles, int order)
 {
     constexpr int kXcds = 8;
+    if (order == 2) {
+        constexpr int kRot = 64;
+        const int blk = b / kRot, base = blk * kRot;
+        const int len = ntiles - base < kRot ? ntiles - base : kRot;
+        int t = (b - base) + (len == kRot ? (blk & (kRot - 1)) : blk % len);
+        if (t >= len) t -= len;
+        return base + t;
+    }
     const int q = ntiles / kXcds;
     if (order == 0 || b >= q * kXcds) return b;
     return (b % kXcds) * q + b / kXcds;

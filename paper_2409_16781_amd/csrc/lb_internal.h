@@ -111,7 +111,8 @@ struct StepArgs {
     int nslots;               // rows * pitch / sites_per_thread
     int lds_edges;            // 1: x-edge elements held by a lane of the same tile pass through LDS
     int lg_row_lanes;         // log2(lanes per x-row) (in-place steps: every tile holds whole rows)
-    int tile_order;           // 0: tile = workgroup index; 1: contiguous tile ranges per XCD
+    int tile_order;           // 0: tile = workgroup index; 1: contiguous tile ranges per XCD; 2: blocks
+                              // of 64 tiles rotated by their index
     int pull_nt;              // host side: 1 = a plain step with solids runs the kernel that pulls with
                               // non-temporal loads (launch_step picks it)
     FastDiv div_pitch, div_ny;

@@ -326,7 +326,7 @@ def test_tune_keeps_the_state_and_picks_a_valid_shape(codec):
     raw, tot = lat.get_f(), lat.sums(7)
     info = lat.tune(5)
     say(f"  {codec}: tuned shape variant={info['variant']} tile_order={info['tile_order']} grid={info['grid']}")
-    assert info["variant"] in (1, 2, 3) and info["tile_order"] in (0, 1) and info["pull_nt"] in (0, 1)
+    assert info["variant"] in (1, 2, 3) and info["tile_order"] in (0, 1, 2) and info["pull_nt"] in (0, 1)
     assert np.array_equal(lat.get_f(), raw) and np.array_equal(lat.sums(7), tot) and lat.steps_done == 7
     lat.step(43)
     _, u = lat.macros()
@@ -334,6 +334,38 @@ def test_tune_keeps_the_state_and_picks_a_valid_shape(codec):
     err = rel_l2_u(u.double().cpu().numpy(), u_ref, fluid_mask(cfg))
     assert err <= (1e-5 if codec == "f32" else 2e-3), err
     lat.close()
+
+
+@pytest.mark.parametrize("codec,variant", [("f32", 1), ("f32", 3), ("f16", 2)])
+def test_tile_orders_give_the_same_state(codec, variant):
+    """Tile orders 0 (linear), 1 (a contiguous range per XCD) and 2 (blocks
+    of 64 tiles rotated) map workgroups to tiles by bijections: the same
+    state bit for bit, and totals equal up to the order of the FP64 sum.
+    The lattice has a partial last block of tiles."""
+    cfg = _porous(64, 36, 30, 0.1, 29)
+    lats = []
+    for order in ("0", "1", "2"):
+        old = os.environ.get("LB_TILE_ORDER")
+        os.environ["LB_TILE_ORDER"] = order
+        try:
+            lat = make_lattice(cfg, codec, variant)
+        finally:
+            if old is None:
+                os.environ.pop("LB_TILE_ORDER", None)
+            else:
+                os.environ["LB_TILE_ORDER"] = old
+        assert lat.info["tile_order"] == int(order) and lat.info["variant"] == variant
+        say(f"[gpu] tile order {order} {codec} variant={variant} grid={lat.info['grid']}")
+        lat.step(3)
+        lat.step(70)
+        lats.append(lat)
+    ref = lats[0].get_f()
+    tot = lats[0].sums(73)
+    for lat in lats[1:]:
+        assert np.array_equal(lat.get_f(), ref)
+        assert np.allclose(lat.sums(73), tot, rtol=1e-12, atol=1e-12)
+    for lat in lats:
+        lat.close()
 
 
 @pytest.mark.parametrize("codec,variant", [("f32", 1), ("f32", 3), ("f16", 2), ("bf16", 1), ("s16", 2), ("s16", 3)])
