@@ -270,7 +270,8 @@ int lb_time_step_kernel(lb_lattice *lat, int n, double *ms);
  * divides nx (16-, 8- and 4-byte accesses per lane) and the three tile
  * orders (lb_query key 11), with solids also both
  * cache policies of the pull loads (cached, or non-temporal), reps launches
- * each, and keep the fastest for this lattice (lb_query keys 0, 4, 11 and 12
+ * each in two passes over the candidates, and keep the fastest for this
+ * lattice (lb_query keys 0, 4, 11 and 12
  * report it).  Each
  * timing launch reads the current state and writes the other array, so the
  * state, the step count and the totals are unchanged.  Synchronises.  Not for

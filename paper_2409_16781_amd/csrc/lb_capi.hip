@@ -1277,6 +1277,10 @@ int lb_tune(lb_lattice *h, int reps)
     HIP_OR_FAIL(evs.create());
     const int saved_variant = h->variant, saved_order = h->tile_order, saved_nt = h->pull_nt;
     int rc = LB_OK;
+    // two passes over the candidates, each keeping its faster timing (drift
+    // of the clocks during the sweep then favours no candidate)
+    for (Cand &c : cands) c.ms = 1e30;
+    for (int pass = 0; pass < 2 && rc == LB_OK; ++pass)
     for (Cand &c : cands) {
         h->variant = c.variant;
         h->tile_order = c.order;
@@ -1305,7 +1309,7 @@ int lb_tune(lb_lattice *h, int reps)
         float t = 0.0f;
         if (rc == LB_OK && hipEventSynchronize(evs[1]) != hipSuccess) rc = fail(LB_EHIP, "hipEventSynchronize");
         if (rc == LB_OK && hipEventElapsedTime(&t, evs[0], evs[1]) != hipSuccess) rc = fail(LB_EHIP, "hipEventElapsedTime");
-        c.ms = (double)t / reps;
+        c.ms = std::min(c.ms, (double)t / reps);
         if (rc != LB_OK) break;
     }
     (void)hipStreamSynchronize(h->stream);
