@@ -18,7 +18,7 @@ import pytest
 import oracle
 import paper_2409_16781_amd as lbm
 from paper_2409_16781_amd import inputs
-from gpu_util import kernel_variant, require_gpu, say
+from gpu_util import W19, kernel_variant, require_gpu, say
 
 pytestmark = pytest.mark.gpu
 
@@ -116,13 +116,36 @@ def test_gradient_matches_oracle(small_ref, variant):
     lat.close()
 
 
-def test_checkpoint_interval_does_not_change_the_gradient():
+@pytest.mark.parametrize("every", [1, 4, 7, 50])
+def test_checkpoint_interval_does_not_change_the_gradient(every):
+    """Recomputed stretches give the moments the forward pass gave: the same
+    gradient bits for one stretch (every = 30 or more), stretches of one
+    step (each recomputed step writes its moments only), and a shorter last
+    stretch."""
     c = small_case(steps=30)
     g1, l1 = gpu_gradient(c, every=30)
-    g2, l2 = gpu_gradient(c, every=4)
+    g2, l2 = gpu_gradient(c, every=every)
     assert np.array_equal(g1, g2)
     l1.close()
     l2.close()
+
+
+def test_outlet_flux_with_a_partial_last_workgroup_of_rows():
+    """lb_outlet_flux sums in two passes (one row per lane, a part per
+    workgroup, then the parts in order). ny * nz = 1200 rows leave a partial
+    last workgroup; the value equals the oracle's flux of the same stored
+    state up to FP64 rounding."""
+    c = small_case(nx=24, ny=40, nz=30, steps=10, seed=5)
+    lat = gpu_lattice(c)
+    lat.step(c["steps"])
+    J = float(lbm.outlet_flux(lat))
+    S = lat.get_f().astype(np.float64) + W19.reshape(19, 1, 1, 1)
+    # the library holds the uniform force in FP32 (the kernels' arithmetic)
+    F32 = tuple(float(np.float32(f)) for f in c["force"])
+    J_ref = oracle.outlet_flux(S, F=F32, flags=c["flags"], Fx_field=c["fx"].astype(np.float64))
+    say(f"  outlet flux 24x40x30: {J:.12e} (oracle of the same state {J_ref:.12e})")
+    assert abs(J - J_ref) <= 1e-12 * max(1.0, abs(J_ref))
+    lat.close()
 
 
 def test_lattice_ends_where_lb_step_ends():
