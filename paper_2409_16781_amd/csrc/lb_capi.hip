@@ -909,8 +909,8 @@ int grad_impl(lb_lattice *h, int nsteps, int every, const float *seed, float *gr
     // Device memory of the sweep: the checkpoints, two states for the
     // recomputed stretches, the two adjoint arrays (the first also takes the
     // seed), and the moments of one stretch's steps (a 16-byte record per
-    // site and step).  The buffers are kept by the lattice and reused by later calls
-    // that need no more of them.
+    // site and step).  The buffers are kept by the lattice and reused by
+    // later calls that need no more of them.
     const size_t need = (size_t)nck + 4;
     while (h->adj_ws.size() < need) {
         void *p = nullptr;
