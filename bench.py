@@ -313,9 +313,14 @@ def run_small(torch, lbm, reps, steps=0):
             lat.close()
             nf = entry.get("fluid_sites", n)  # algorithmic bytes: fluid sites only
             kgbs = bytes_per_site(codec) * nf / (kernel_ms * 1e-3) / 1e9
+            gbs = bytes_per_site(codec) * nf * cfg["steps"] / (ms * 1e-3) / 1e9
+            # kernel_ms: HIP events around single eagerly launched kernels,
+            # which on steps of tens of microseconds include a few
+            # microseconds of launch; the step rate of the captured run
+            # (gbs_algorithmic, frac_hbm) carries no such overhead
             entry[codec] = dict(mlups=round(n * cfg["steps"] / (ms * 1e-3) / 1e6, 1),
                                 ms_per_step=round(ms / cfg["steps"], 5),
-                                gbs_algorithmic=round(bytes_per_site(codec) * nf * cfg["steps"] / (ms * 1e-3) / 1e9, 1),
+                                gbs_algorithmic=round(gbs, 1), frac_hbm=round(gbs / HBM_PEAK_GBS, 4),
                                 kernel_ms=round(kernel_ms, 5), kernel_gbs=round(kgbs, 1),
                                 kernel_frac_hbm=round(kgbs / HBM_PEAK_GBS, 4),
                                 shape={k: shape[k] for k in ("variant", "sites_per_thread", "tile_order", "pull_nt", "grid")},
