@@ -413,7 +413,7 @@ def cpu_model():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU (the step of one lattice on one device); --gpus must be 1"}))
         sys.exit(2)
     import torch
     import paper_2409_16781_amd as lbm
